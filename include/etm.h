@@ -1,0 +1,228 @@
+/*
+ * etm.h - C ABI of the MI355X (gfx950) transient EM-thermal-mechanical
+ * package solver: the data-parallel hot path of arXiv 2603.07038, Sec. II.
+ *
+ * One plan = one package design: a rectilinear voxel mesh with one material
+ * per cell, a material table, port edges with sampled excitations and run
+ * options.  The plan marches
+ *   1. the EM field by the explicit central-difference update, Eq. (2)-(3),
+ *      with sigma(T) from Eq. (6);
+ *   2. the Joule source P = D_sigma e^2 (Sec. II-A, below Eq. 4);
+ *   3. transient conduction by forward Euler, Eq. (4)-(5), every R EM steps
+ *      with the block-mean Joule source (R = 1 is the paper's schedule);
+ *   4. the thermoelastic HEX8 system, Eq. (7)-(8), by Jacobi-preconditioned
+ *      CG, and the centroid von Mises stress, Eq. (9);
+ * on one GPU.  Device memory is owned by the caller (e.g. a torch tensor)
+ * and handed to the plan as one workspace; all GPU work is enqueued on the
+ * caller's HIP stream.
+ *
+ * Conventions
+ *  - Every function returns etm_status (ETM_OK = 0, errors < 0) and never
+ *    aborts or prints; etm_last_error() gives a thread-local message.
+ *  - Host inputs are borrowed for the duration of the call and deep-copied.
+ *  - Spatial arrays handed in or out are C-ordered with x fastest in their
+ *    natural shapes: cells (nz,ny,nx); nodes (nz+1,ny+1,nx+1); x-edges
+ *    (nz+1,ny+1,nx); y-edges (nz+1,ny,nx+1); z-edges (nz,ny+1,nx+1).  The
+ *    x-edge (i,j,k) joins nodes (i,j,k) and (i+1,j,k); likewise y and z.
+ *  - SI units.  Temperature is carried as the rise theta = T - T0.
+ */
+#ifndef ETM_H
+#define ETM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t etm_status;
+enum {
+    ETM_OK = 0,
+    ETM_E_INVAL = -1,    /* malformed argument, mesh, material, port or option */
+    ETM_E_NOMEM = -2,    /* workspace too small / host allocation failed */
+    ETM_E_HIP = -3,      /* a HIP runtime call failed */
+    ETM_E_UNSTABLE = -4, /* dt above the CFL limit, explicit thermal step unstable, or non-finite field */
+    ETM_E_NOCONV = -5,   /* the mechanical CG did not reach its tolerance within cg_maxit */
+    ETM_E_STATE = -6     /* call out of order (e.g. advance before bind) */
+};
+
+enum { ETM_PMC = 0, ETM_PEC = 1 };                          /* EM face condition */
+enum { ETM_MECH_KINEMATIC = 0, ETM_MECH_CLAMP_ZMIN = 1 };   /* mechanical support */
+enum { ETM_PREC_FP64 = 0, ETM_PREC_MIXED = 1 };             /* arithmetic of the path */
+
+/* Fields for etm_read / etm_write (always FP64, natural shapes). */
+enum {
+    ETM_FIELD_EX = 0, ETM_FIELD_EY = 1, ETM_FIELD_EZ = 2,          /* e^n                 */
+    ETM_FIELD_EX_PREV = 3, ETM_FIELD_EY_PREV = 4, ETM_FIELD_EZ_PREV = 5, /* e^{n-1}     */
+    ETM_FIELD_THETA = 6,   /* temperature rise on nodes                                  */
+    ETM_FIELD_PSUM = 7,    /* sum of the Joule power density over the open thermal block */
+    ETM_FIELD_UX = 8, ETM_FIELD_UY = 9, ETM_FIELD_UZ = 10,          /* displacement      */
+    ETM_FIELD_VM = 11,     /* von Mises stress per cell (read only)                       */
+    ETM_FIELD_FX = 12, ETM_FIELD_FY = 13, ETM_FIELD_FZ = 14         /* thermal load (read only) */
+};
+
+/* One material (a row of the table indexed by the per-cell id).
+ * eps_r relative permittivity; sigma0 conductivity at T0 [S/m]; tcr
+ * temperature coefficient of resistance [1/K] (Eq. 6); k thermal
+ * conductivity [W/m/K]; rho_cp volumetric heat capacity [J/m^3/K]; E Young's
+ * modulus [Pa]; nu Poisson ratio; cte linear expansion [1/K]; is_void != 0
+ * marks a cell without stiffness (air). */
+typedef struct {
+    double eps_r, sigma0, tcr, k, rho_cp, E, nu, cte;
+    int32_t is_void;
+    int32_t reserved;
+} etm_material;
+
+/* Rectilinear mesh: cell widths dx[nx], dy[ny], dz[nz] in metres (all > 0)
+ * and one material id per cell, mat[(k*ny + j)*nx + i] < n_mat. */
+typedef struct {
+    int32_t nx, ny, nz;
+    const double *dx, *dy, *dz;
+    const uint8_t *mat;
+} etm_mesh;
+
+/* A port edge: direction dir (0/1/2 = x/y/z) starting at node (i,j,k).
+ * The edge carries the impressed current density weight * J_wave(t) [A/m^2]
+ * and the lumped conductance g [S/m] added to its conductivity in the
+ * update (the Norton form of a resistive source).  g does not heat. */
+typedef struct {
+    int32_t dir, i, j, k, wave;
+    int32_t reserved;
+    double weight, g;
+} etm_port;
+
+/* Sampled excitations: J_half[w*n_samples + s] = J_w((s - 1/2) dt), so EM
+ * step n (making e^{n+1}) uses samples n+1 and n; samples beyond the array
+ * are taken as zero.  Column 0 (t = -dt/2) is zero for a causal source. */
+typedef struct {
+    int64_t n_ports;
+    const etm_port *ports;
+    int32_t n_waves;
+    int64_t n_samples;
+    const double *J_half;
+} etm_source;
+
+/* Run options.  Fill with etm_opts_default() first. */
+typedef struct {
+    double dt;                  /* EM step [s]; 0 = cfl * CFL limit */
+    double cfl;                 /* Courant number used when dt == 0 (default 0.9) */
+    int32_t force_dt;           /* accept dt above the CFL limit (for failure tests) */
+    int32_t precision;          /* ETM_PREC_FP64 or ETM_PREC_MIXED */
+    int32_t em_bc[6];           /* -x,+x,-y,+y,-z,+z: ETM_PMC or ETM_PEC */
+    int32_t em_per_thermal;     /* R: EM steps per thermal step (>= 1) */
+    int32_t mech_every_thermal; /* m > 0: mechanical solve after every m-th thermal step; 0: only on request */
+    int32_t mech_bc;            /* ETM_MECH_KINEMATIC or ETM_MECH_CLAMP_ZMIN */
+    const uint8_t *mech_mask;   /* optional per-node fixed-DOF bits (1=x,2=y,4=z), node shape; overrides mech_bc */
+    int32_t cg_maxit;           /* CG iteration limit per solve (default 200000) */
+    double cg_rtol;             /* ||f - K u||_2 <= cg_rtol ||f||_2 on the FP64 residual (default 1e-8) */
+    int32_t history_stride;     /* record histories every stride EM steps (0 = never) */
+    int32_t n_probes;           /* probes[4*p..] = field (0..2 = ex,ey,ez; 3 = theta), i, j, k */
+    const int64_t *probes;
+    int64_t history_cap;        /* records kept (0 = enough for n_em_steps_hint) */
+    int64_t n_em_steps_hint;    /* expected run length (sizes the history) */
+} etm_opts;
+
+/* What etm_sync reports. */
+typedef struct {
+    int64_t step;          /* EM steps done */
+    int32_t status;        /* first asynchronous error seen (ETM_OK if none) */
+    int32_t cg_iters;      /* iterations of the last mechanical solve (inner, all refinements) */
+    int32_t cg_outer;      /* FP64 residual evaluations of the last solve */
+    int32_t n_solves;      /* mechanical solves so far */
+    double cg_relres;      /* final ||f - K u|| / ||f|| of the last solve */
+    double theta_max;      /* max temperature rise */
+    double ejoule;         /* dissipated EM energy so far [J] */
+    int64_t n_records;     /* history records available */
+    int64_t cg_iters_total;/* inner CG iterations over all solves */
+} etm_run_info;
+
+typedef struct etm_plan etm_plan;
+typedef struct etm_batch etm_batch;
+
+/* Default options: dt auto at CFL 0.9, FP64, all faces PMC, R = 1, no
+ * scheduled mechanics, kinematic mount, rtol 1e-8. */
+etm_status etm_opts_default(etm_opts *opts);
+
+/* CFL-limited step for a mesh (Eq. 2 is constrained by CFL, Sec. II-A):
+ * dt = cfl / (c0 sqrt(1/dx_min^2 + 1/dy_min^2 + 1/dz_min^2)). */
+etm_status etm_cfl_dt(const etm_mesh *mesh, double cfl, double *dt);
+
+/* Validate and copy all inputs; derive tables, DOF maps, constraints and the
+ * workspace layout.  Host only.  ETM_E_INVAL on malformed input,
+ * ETM_E_UNSTABLE when dt exceeds the CFL limit (unless force_dt) or the
+ * explicit thermal step R*dt exceeds its forward-Euler bound. */
+etm_status etm_plan_create(const etm_mesh *mesh, const etm_material *mats, int32_t n_mat,
+                           const etm_source *src, const etm_opts *opts, etm_plan **out);
+
+/* Device bytes the plan needs in its workspace (256-byte aligned start). */
+etm_status etm_plan_footprint(const etm_plan *plan, size_t *device_bytes);
+
+/* The EM step in use [s]. */
+etm_status etm_plan_dt(const etm_plan *plan, double *dt);
+
+/* DOF counts: EM edges (PEC edges included), thermal nodes, mechanical node DOFs (3 per node). */
+etm_status etm_plan_dofs(const etm_plan *plan, int64_t *em, int64_t *thermal, int64_t *mech);
+
+/* Attach caller-owned device memory (>= footprint bytes, 256-byte aligned)
+ * and a hipStream_t (NULL = default stream).  Uploads the tables, zeroes the
+ * state (e = 0, theta = 0) and enqueues everything on the stream.  May be
+ * called again to move the plan to a new workspace (state is reset). */
+etm_status etm_plan_bind(etm_plan *plan, void *device_ws, size_t bytes, void *hip_stream);
+
+/* Enqueue n_em_steps coupled steps (EM + Joule + thermal every R steps +
+ * histories; scheduled mechanical solves run at their thermal steps and
+ * wait on the host for convergence).  Asynchronous errors are reported by
+ * etm_sync. */
+etm_status etm_advance(etm_plan *plan, int64_t n_em_steps);
+
+/* Solve Eq. (8) for the current temperature (warm-started from the last
+ * displacement) and evaluate Eq. (9).  Polls the device for convergence. */
+etm_status etm_mech_solve(etm_plan *plan);
+
+/* Wait for the plan's stream; fill info (may be NULL); return the first
+ * asynchronous error (ETM_E_UNSTABLE on a non-finite field, ETM_E_NOCONV). */
+etm_status etm_sync(etm_plan *plan, etm_run_info *info);
+
+/* Copy a field out as FP64 in its natural shape (bytes must equal the
+ * field's size * 8).  dst_is_device != 0: dst is device memory. */
+etm_status etm_read(const etm_plan *plan, int32_t field, void *dst, size_t bytes, int32_t dst_is_device);
+
+/* Overwrite a state field (EX..PSUM, UX..UZ) from FP64 natural-shape data. */
+etm_status etm_write(etm_plan *plan, int32_t field, const void *src, size_t bytes, int32_t src_is_device);
+
+/* Histories: rows of [step, W, cumulative Joule energy, max theta, probes...]
+ * where W = 1/2 [(e^{n+1}-e^n)^T D_eps (e^{n+1}-e^n)/dt^2 + e^{n+1 T} S e^n]
+ * is the discrete energy Eq. (2) conserves without loss or source.
+ * *n_rows receives the number of rows copied. */
+etm_status etm_read_history(const etm_plan *plan, double *dst, size_t bytes, int64_t *n_rows);
+
+/* Checkpoint / restore the whole march state (step, fields, block sum,
+ * Joule energy, displacement) through host memory; a restored plan
+ * continues bitwise identically. */
+etm_status etm_checkpoint_size(const etm_plan *plan, size_t *bytes);
+etm_status etm_checkpoint(const etm_plan *plan, void *dst, size_t bytes);
+etm_status etm_restore(etm_plan *plan, const void *src, size_t bytes);
+
+/* Destroy the plan (does not free the caller's workspace). */
+void etm_plan_destroy(etm_plan *plan);
+
+/* ---- batched design variants (one launch per step over all variants) ----
+ * A batch holds up to max_slots bound plans.  etm_batch_advance enqueues
+ * n_em_steps steps of every attached plan on one stream: each EM step is a
+ * single launch that walks a (variant, tile) work list, each thermal block a
+ * single launch; chunks of steps are captured once in a HIP graph and
+ * replayed.  A variant's results are bitwise those of its solo run.
+ * tune_json may name per-shape tile choices ("{}" or NULL: defaults). */
+etm_status etm_batch_create(int32_t max_slots, const char *tune_json, etm_batch **out);
+etm_status etm_batch_attach(etm_batch *batch, etm_plan *plan, int32_t *slot);
+etm_status etm_batch_detach(etm_batch *batch, int32_t slot);
+etm_status etm_batch_advance(etm_batch *batch, int64_t n_em_steps, void *hip_stream);
+void etm_batch_destroy(etm_batch *batch);
+
+const char *etm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ETM_H */

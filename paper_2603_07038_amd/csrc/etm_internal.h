@@ -1,0 +1,169 @@
+// Private declarations shared by the host plan and the gfx950 kernels.
+//
+// Device layout: every per-node, per-edge and per-cell array uses one padded
+// node-shaped index  n = k*sz + j*sy + i  (x fastest, row pitch sy a multiple
+// of 16 elements, plane pitch sz = sy*(ny+1)).  The x-edge, y-edge and
+// z-edge starting at node (i,j,k) and the cell whose low corner is node
+// (i,j,k) all live at index n of their own arrays; entries that do not exist
+// (i == nx for an x-edge, ...) are kept at zero and never updated.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "etm.h"
+
+namespace etm {
+
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kMu0 = 1.25663706212e-6;
+constexpr double kC0 = 299792458.0;
+constexpr int kPad = 16;        // row pitch multiple (elements)
+constexpr int kMatStride = 16;  // doubles per material row on the device
+
+// Device material row (scaled for the EM update at the plan's dt).
+enum MatCol {
+  MC_EPSR = 0,    // relative permittivity
+  MC_SIGS = 1,    // sigma0 * dt / (2 eps0): the a-coefficient of Eq. (3) per unit eps0
+  MC_TCR = 2,     // temperature coefficient of resistance (Eq. 6)
+  MC_K = 3,       // thermal conductivity
+  MC_RHOCP = 4,   // volumetric heat capacity
+  MC_LAMBDA = 5,  // Lame lambda
+  MC_MU = 6,      // Lame mu
+  MC_BETA = 7,    // (3 lambda + 2 mu) * cte: thermal stress per unit rise
+  MC_CTE = 8,
+  MC_VOID = 9,    // 1 for a cell without stiffness
+};
+
+// Grid description passed by value to every kernel.
+struct DevGrid {
+  int nx, ny, nz;
+  int n_mat;
+  int64_t sy, sz, ntot;  // row pitch, plane pitch, padded node count
+  const double *dx, *dy, *dz;     // cell widths
+  const double *idx, *idy, *idz;  // 1 / width
+  const double *hx, *hy, *hz;     // node-centred widths (half cells at the ends)
+  const double *ihx, *ihy, *ihz;  // 1 / node-centred width
+  const uint8_t *mat;             // cell material ids
+  const uint8_t *flags;           // per node: bit d = the d-edge from this node is a port edge
+  const double *mtab;             // n_mat rows of kMatStride
+  int pec;                        // bit f = face f (-x,+x,-y,+y,-z,+z) is PEC
+};
+
+// Port edges, sorted by key = dir * ntot + node.  Entry p has lumped
+// conductance gs[p] (scaled like MC_SIGS) and source terms
+// [start[p], start[p+1]) of (wave, weight * dt / eps0).
+struct DevPorts {
+  int n_edges;
+  const int64_t *key;
+  const double *gs;
+  const int32_t *start;
+  const int32_t *wave;
+  const double *wt;
+  const double *J;    // [n_waves][n_samples]
+  int64_t n_samples;
+};
+
+// Scalars kept on the device for a plan.
+struct DevScalars {
+  double ejoule;      // dissipated energy of completed thermal blocks [J]
+  double theta_max;
+  int32_t status;     // first asynchronous error
+  int32_t pad0;
+  int64_t n_records;
+  // CG
+  double rz, pw, alpha, beta, rr, tol2;
+  int32_t done, iters;
+  double fnorm2;
+};
+
+// Reduction partials: per block, up to 4 doubles.
+constexpr int kRedWidth = 4;
+
+// ---- launchers (kernels in em.hip, mech.hip) ------------------------------
+struct EmLaunch {
+  DevGrid g;
+  DevPorts ports;
+  int precision;          // ETM_PREC_FP64 / ETM_PREC_MIXED
+  double c2dt2;           // (c0 dt)^2
+  double jf;              // eps0 / dt: Joule factor on e^2 * L * sigma_s-area sums
+  int64_t step;           // n of the step being made (e^{n} -> e^{n+1})
+  // FP64: e0 = e^n, e1 = e^{n-1}, out = e^{n+1}
+  // MIXED: e0 = e^n (float), d0 = delta^{n-1/2}, out_e / out_d
+  const void *e0[3];
+  const void *e1[3];
+  void *out0[3];
+  void *out1[3];
+  const double *theta;    // FP64 rise (FP64 path)
+  const float *theta32;   // FP32 copy (mixed path)
+  double *psum;
+};
+hipError_t launch_em_step(const EmLaunch &L, hipStream_t s);
+
+struct ThermalLaunch {
+  DevGrid g;
+  double dt;              // EM step
+  int R;                  // EM steps in the block
+  const double *theta_in;
+  double *theta_out;
+  float *theta32;         // refreshed copy (may be null)
+  double *psum;           // zeroed
+  double *partials;       // per block: [energy, max]
+  DevScalars *sc;
+};
+hipError_t launch_thermal(const ThermalLaunch &L, hipStream_t s);
+
+struct DiagLaunch {
+  DevGrid g;
+  int precision;
+  double c2dt2, dt;
+  const void *e_new[3];   // e^{n+1}
+  const void *e_old[3];   // FP64: e^n; MIXED: delta^{n+1/2}
+  const double *theta;
+  const double *psum;
+  double *partials;
+  DevScalars *sc;
+  double *hist_row;       // row to write
+  int n_probes;
+  const int64_t *probes;  // device: [field, node index] pairs
+  int64_t step;
+  int64_t cap, rec;
+};
+hipError_t launch_diag(const DiagLaunch &L, hipStream_t s);
+
+hipError_t launch_pack(const void *src, int src_f32, int64_t sy, int64_t sz, int ni, int nj, int nk,
+                       double *dst, hipStream_t s);
+hipError_t launch_unpack(const double *src, int ni, int nj, int nk, void *dst, int dst_f32, int64_t sy,
+                         int64_t sz, hipStream_t s);
+hipError_t launch_fill(void *dst, int64_t n_bytes, hipStream_t s);
+
+// Mechanics.
+struct MechGrid {
+  DevGrid g;
+  const uint8_t *fixed;   // per node: bit c = DOF c fixed
+};
+hipError_t launch_mech_diag(const MechGrid &M, double *dinv[3], hipStream_t s);
+hipError_t launch_mech_rhs(const MechGrid &M, const double *theta, double *f[3], double *partials,
+                           DevScalars *sc, double rtol, hipStream_t s);
+// CG building blocks (T = double or float vectors; scalars in double).
+template <typename T>
+struct CgVecs {
+  T *u[3], *r[3], *p[3], *w[3];
+  const T *dinv[3];
+};
+template <typename T>
+hipError_t launch_cg_setup(const MechGrid &M, const CgVecs<T> &v, const T *rhs[3], double *partials,
+                           DevScalars *sc, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_iteration(const MechGrid &M, const CgVecs<T> &v, double *partials, DevScalars *sc,
+                               hipStream_t s);
+// FP64 true residual r64 = f - K u64, its norm into sc (rr), for refinement.
+hipError_t launch_residual64(const MechGrid &M, const double *f[3], const double *u[3], double *r[3],
+                             double *partials, DevScalars *sc, hipStream_t s);
+hipError_t launch_vec_cast(const void *src, int src_f32, void *dst, int dst_f32, int64_t n, hipStream_t s);
+hipError_t launch_vec_axpy64(double *y, const float *x, int64_t n, hipStream_t s);  // y += x
+hipError_t launch_von_mises(const MechGrid &M, const double *theta, const double *u[3], double *vm,
+                            hipStream_t s);
+
+int reduce_blocks(int64_t ntot);
+
+}  // namespace etm

@@ -1,0 +1,477 @@
+// gfx950 kernels of the thermoelastic solve (arXiv 2603.07038, Sec. II-B):
+// the HEX8 stiffness of Eq. (8) applied matrix-free, its thermal load, the
+// Jacobi-preconditioned CG that replaces the paper's closed AMG solver, and
+// the centroid von Mises stress of Eq. (9).
+//
+// Box elements.  Every cell is an axis-aligned box, so with trilinear shape
+// functions N_a = phi_ax(x) phi_ay(y) phi_az(z) each entry of the element
+// matrices factors into 1D integrals
+//   m(a,b) = int phi_a phi_b  = h/3 (a == b) or h/6,
+//   k(a,b) = int phi_a' phi_b' = +1/h or -1/h,
+//   int phi_a' phi_b = s_a / 2   (s_0 = -1, s_1 = +1),
+// and the 2x2x2 Gauss rule of the paper integrates all of them exactly
+// (at most quadratic per axis).  With A^IJ_ab = int dN_a/dx_I dN_b/dx_J,
+// the 3x3 block of the element stiffness is
+//   K_IJ(a,b) = lambda A^IJ + mu A^JI + delta_IJ mu (A^xx + A^yy + A^zz),
+// and the thermal load is f_aI = (3 lambda + 2 mu) cte sum_b theta_b
+// int dN_a/dx_I N_b  (theta trilinear, as at the Gauss points).
+//
+// One thread owns one node and gathers the rows of its 8 cells (no atomics).
+// Vectors are SoA node-shaped arrays; fixed DOFs hold zero and their rows
+// return zero, which restricts the operator to the free DOFs.
+#include <algorithm>
+
+#include "etm_internal.h"
+
+namespace etm {
+
+namespace {
+
+constexpr int BX = 64, BY = 4;
+
+inline dim3 node_grid(const DevGrid &g) { return dim3((g.nx + 1 + BX - 1) / BX, (g.ny + 1 + BY - 1) / BY, g.nz + 1); }
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block sums of NS values into out[0..NS) (any block size that is a multiple of 64, <= 1024).
+template <int NS>
+__device__ __forceinline__ void block_sums(const double (&v)[NS], double *out) {
+  __shared__ double red[16][NS];
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  double r[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) r[q] = wsum(v[q]);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NS; ++q) red[wv][q] = r[q];
+  __syncthreads();
+  if (tid == 0) {
+    const int nw = (blockDim.x * blockDim.y) / 64;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      double acc = red[0][q];
+      for (int w = 1; w < nw; ++w) acc += red[w][q];
+      out[q] = acc;
+    }
+  }
+}
+
+// Fixed-order sum of partials[nb][kRedWidth] columns 0..NS-1 by one block of 256.
+template <int NS>
+__device__ __forceinline__ void sum_partials(const double *part, int64_t nb, double *out) {
+  double v[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) v[q] = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < NS; ++q) v[q] += part[b * kRedWidth + q];
+  block_sums<NS>(v, out);
+}
+
+// K_e rows of local node a applied to the cell's nodal vectors, accumulated
+// into y.  pv[3] point at the node-shaped input arrays; nb0 is the index of
+// the cell's low corner node.
+template <typename T>
+__device__ __forceinline__ void cell_rows(const DevGrid &g, int ci, int cj, int ck, int ax, int ay, int az,
+                                          int64_t nb0, const T *const *pv, T &yx, T &yy, T &yz) {
+  const double *row = g.mtab + g.mat[nb0] * kMatStride;
+  if (row[MC_VOID] != 0.0) return;
+  const T lam = T(row[MC_LAMBDA]), mu = T(row[MC_MU]);
+  const T hx = T(g.dx[ci]), hy = T(g.dy[cj]), hz = T(g.dz[ck]);
+  const T ihx = T(g.idx[ci]), ihy = T(g.idy[cj]), ihz = T(g.idz[ck]);
+  const T gax = ax ? T(0.5) : T(-0.5), gay = ay ? T(0.5) : T(-0.5), gaz = az ? T(0.5) : T(-0.5);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+    const int64_t nb = nb0 + bx + by * g.sy + bz * g.sz;
+    const T px = pv[0][nb], py = pv[1][nb], pz = pv[2][nb];
+    const bool sx = ax == bx, sy = ay == by, sz = az == bz;
+    const T mx = hx * (sx ? T(1.0 / 3.0) : T(1.0 / 6.0)), my = hy * (sy ? T(1.0 / 3.0) : T(1.0 / 6.0)),
+            mz = hz * (sz ? T(1.0 / 3.0) : T(1.0 / 6.0));
+    const T kx = sx ? ihx : -ihx, ky = sy ? ihy : -ihy, kz = sz ? ihz : -ihz;
+    const T gbx = bx ? T(0.5) : T(-0.5), gby = by ? T(0.5) : T(-0.5), gbz = bz ? T(0.5) : T(-0.5);
+    const T Axx = kx * my * mz, Ayy = mx * ky * mz, Azz = mx * my * kz;
+    const T Lp = mu * (Axx + Ayy + Azz);
+    const T Axy = gax * gby * mz, Ayx = gay * gbx * mz;
+    const T Axz = gax * my * gbz, Azx = gaz * my * gbx;
+    const T Ayz = mx * gay * gbz, Azy = mx * gaz * gby;
+    yx += ((lam + mu) * Axx + Lp) * px + (lam * Axy + mu * Ayx) * py + (lam * Axz + mu * Azx) * pz;
+    yy += (lam * Ayx + mu * Axy) * px + ((lam + mu) * Ayy + Lp) * py + (lam * Ayz + mu * Azy) * pz;
+    yz += (lam * Azx + mu * Axz) * px + (lam * Azy + mu * Ayz) * py + ((lam + mu) * Azz + Lp) * pz;
+  }
+}
+
+// y = K p at node (i,j,k) = index n (free rows only).
+template <typename T>
+__device__ __forceinline__ void node_apply(const MechGrid &M, int i, int j, int k, int64_t n, const T *const *pv,
+                                           T &yx, T &yy, T &yz) {
+  const DevGrid &g = M.g;
+  yx = yy = yz = T(0);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+    const int ci = i - 1 + ox, cj = j - 1 + oy, ck = k - 1 + oz;
+    if (ci < 0 || ci >= g.nx || cj < 0 || cj >= g.ny || ck < 0 || ck >= g.nz) continue;
+    const int64_t nb0 = n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz;
+    cell_rows<T>(g, ci, cj, ck, 1 - ox, 1 - oy, 1 - oz, nb0, pv, yx, yy, yz);
+  }
+  const uint8_t f = M.fixed[n];
+  if (f & 1) yx = T(0);
+  if (f & 2) yy = T(0);
+  if (f & 4) yz = T(0);
+}
+
+__global__ __launch_bounds__(256) void mech_diag_kernel(MechGrid M, double *d0, double *d1, double *d2) {
+  const DevGrid &g = M.g;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i > g.nx || j > g.ny) return;
+  const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
+  double sx = 0, sy = 0, sz = 0;
+  for (int c = 0; c < 8; ++c) {
+    const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+    const int ci = i - 1 + ox, cj = j - 1 + oy, ck = k - 1 + oz;
+    if (ci < 0 || ci >= g.nx || cj < 0 || cj >= g.ny || ck < 0 || ck >= g.nz) continue;
+    const double *row = g.mtab + g.mat[n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz] * kMatStride;
+    if (row[MC_VOID] != 0.0) continue;
+    const double lam = row[MC_LAMBDA], mu = row[MC_MU];
+    const double hx = g.dx[ci], hy = g.dy[cj], hz = g.dz[ck];
+    const double Axx = (1.0 / hx) * (hy / 3.0) * (hz / 3.0), Ayy = (hx / 3.0) * (1.0 / hy) * (hz / 3.0),
+                 Azz = (hx / 3.0) * (hy / 3.0) * (1.0 / hz);
+    const double Lp = mu * (Axx + Ayy + Azz);
+    sx += (lam + mu) * Axx + Lp;
+    sy += (lam + mu) * Ayy + Lp;
+    sz += (lam + mu) * Azz + Lp;
+  }
+  const uint8_t f = M.fixed[n];
+  d0[n] = (f & 1) || sx == 0.0 ? 0.0 : 1.0 / sx;
+  d1[n] = (f & 2) || sy == 0.0 ? 0.0 : 1.0 / sy;
+  d2[n] = (f & 4) || sz == 0.0 ? 0.0 : 1.0 / sz;
+}
+
+// Thermal load with fixed rows zeroed; partial ||f||^2 per block.
+__global__ __launch_bounds__(256) void mech_rhs_kernel(MechGrid M, const double *theta, double *f0, double *f1,
+                                                       double *f2, double *partials) {
+  const DevGrid &g = M.g;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  double nrm = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
+    double fx = 0, fy = 0, fz = 0;
+    for (int c = 0; c < 8; ++c) {
+      const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+      const int ci = i - 1 + ox, cj = j - 1 + oy, ck = k - 1 + oz;
+      if (ci < 0 || ci >= g.nx || cj < 0 || cj >= g.ny || ck < 0 || ck >= g.nz) continue;
+      const int64_t nb0 = n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz;
+      const double *row = g.mtab + g.mat[nb0] * kMatStride;
+      if (row[MC_VOID] != 0.0) continue;
+      const double beta = row[MC_BETA];
+      const double hx = g.dx[ci], hy = g.dy[cj], hz = g.dz[ck];
+      const int ax = 1 - ox, ay = 1 - oy, az = 1 - oz;
+      const double gx = ax ? 0.5 : -0.5, gy = ay ? 0.5 : -0.5, gz = az ? 0.5 : -0.5;
+      double sx = 0, sy = 0, sz = 0;
+      for (int b = 0; b < 8; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+        const double th = theta[nb0 + bx + by * g.sy + bz * g.sz];
+        const double mx = hx * (ax == bx ? 1.0 / 3.0 : 1.0 / 6.0), my = hy * (ay == by ? 1.0 / 3.0 : 1.0 / 6.0),
+                     mz = hz * (az == bz ? 1.0 / 3.0 : 1.0 / 6.0);
+        sx += th * my * mz;
+        sy += th * mx * mz;
+        sz += th * mx * my;
+      }
+      fx += beta * gx * sx;
+      fy += beta * gy * sy;
+      fz += beta * gz * sz;
+    }
+    const uint8_t fl = M.fixed[n];
+    if (fl & 1) fx = 0;
+    if (fl & 2) fy = 0;
+    if (fl & 4) fz = 0;
+    f0[n] = fx; f1[n] = fy; f2[n] = fz;
+    nrm = fx * fx + fy * fy + fz * fz;
+  }
+  const double v[1] = {nrm};
+  const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  block_sums<1>(v, partials + b * kRedWidth);
+}
+
+__global__ __launch_bounds__(256) void rhs_finalize(const double *part, int64_t nb, DevScalars *sc, double rtol) {
+  __shared__ double out[1];
+  sum_partials<1>(part, nb, out);
+  if (threadIdx.x == 0) {
+    sc->fnorm2 = out[0];
+    sc->tol2 = rtol * rtol * out[0];
+  }
+}
+
+// ---- CG -----------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void cg_setup_kernel(MechGrid M, CgVecs<T> v, const T *r0, const T *r1,
+                                                       const T *r2, int zero_init, double *partials) {
+  const DevGrid &g = M.g;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  double rz = 0.0, rr = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
+    T yx = T(0), yy = T(0), yz = T(0);
+    if (!zero_init) {
+      const T *pv[3] = {v.u[0], v.u[1], v.u[2]};
+      node_apply<T>(M, i, j, k, n, pv, yx, yy, yz);
+    }
+    const T rx = r0[n] - yx, ry = r1[n] - yy, rzv = r2[n] - yz;
+    const T zx = v.dinv[0][n] * rx, zy = v.dinv[1][n] * ry, zz = v.dinv[2][n] * rzv;
+    v.r[0][n] = rx; v.r[1][n] = ry; v.r[2][n] = rzv;
+    v.p[0][n] = zx; v.p[1][n] = zy; v.p[2][n] = zz;
+    rz = double(rx) * double(zx) + double(ry) * double(zy) + double(rzv) * double(zz);
+    rr = double(rx) * double(rx) + double(ry) * double(ry) + double(rzv) * double(rzv);
+  }
+  const double s[2] = {rz, rr};
+  const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  block_sums<2>(s, partials + b * kRedWidth);
+}
+
+__global__ __launch_bounds__(256) void cg_setup_finalize(const double *part, int64_t nb, DevScalars *sc) {
+  __shared__ double out[2];
+  sum_partials<2>(part, nb, out);
+  if (threadIdx.x == 0) {
+    sc->rz = out[0];
+    sc->rr = out[1];
+    sc->iters = 0;
+    sc->done = (out[1] <= sc->tol2) ? 1 : 0;
+    sc->alpha = sc->beta = 0.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cg_apply_kernel(MechGrid M, CgVecs<T> v, const DevScalars *sc,
+                                                       double *partials) {
+  if (sc->done) return;
+  const DevGrid &g = M.g;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  double pw = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
+    const T *pv[3] = {v.p[0], v.p[1], v.p[2]};
+    T yx, yy, yz;
+    node_apply<T>(M, i, j, k, n, pv, yx, yy, yz);
+    v.w[0][n] = yx; v.w[1][n] = yy; v.w[2][n] = yz;
+    pw = double(v.p[0][n]) * double(yx) + double(v.p[1][n]) * double(yy) + double(v.p[2][n]) * double(yz);
+  }
+  const double s[1] = {pw};
+  const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  block_sums<1>(s, partials + b * kRedWidth);
+}
+
+__global__ __launch_bounds__(256) void cg_alpha_finalize(const double *part, int64_t nb, DevScalars *sc) {
+  if (sc->done) return;
+  __shared__ double out[1];
+  sum_partials<1>(part, nb, out);
+  if (threadIdx.x == 0) {
+    sc->pw = out[0];
+    sc->alpha = out[0] > 0.0 ? sc->rz / out[0] : 0.0;
+    if (!(out[0] > 0.0)) sc->done = 2;  // breakdown: stop (the host re-checks the true residual)
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cg_update_kernel(CgVecs<T> v, int64_t ntot, const DevScalars *sc,
+                                                        double *partials) {
+  if (sc->done) return;
+  const T alpha = T(sc->alpha);
+  double rz = 0.0, rr = 0.0;
+  for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < ntot; n += int64_t(gridDim.x) * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T p = v.p[c][n];
+      v.u[c][n] += alpha * p;
+      const T r = v.r[c][n] - alpha * v.w[c][n];
+      v.r[c][n] = r;
+      const T z = v.dinv[c][n] * r;
+      rz += double(r) * double(z);
+      rr += double(r) * double(r);
+    }
+  }
+  const double s[2] = {rz, rr};
+  block_sums<2>(s, partials + int64_t(blockIdx.x) * kRedWidth);
+}
+
+__global__ __launch_bounds__(256) void cg_beta_finalize(const double *part, int64_t nb, DevScalars *sc) {
+  if (sc->done) return;
+  __shared__ double out[2];
+  sum_partials<2>(part, nb, out);
+  if (threadIdx.x == 0) {
+    sc->iters += 1;
+    sc->rr = out[1];
+    if (out[1] <= sc->tol2 || !(out[0] > 0.0)) {
+      sc->done = 1;
+    } else {
+      sc->beta = out[0] / sc->rz;
+      sc->rz = out[0];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cg_p_kernel(CgVecs<T> v, int64_t ntot, const DevScalars *sc) {
+  if (sc->done) return;
+  const T beta = T(sc->beta);
+  for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < ntot; n += int64_t(gridDim.x) * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v.p[c][n] = v.dinv[c][n] * v.r[c][n] + beta * v.p[c][n];
+  }
+}
+
+__global__ __launch_bounds__(256) void residual64_kernel(MechGrid M, const double *f0, const double *f1,
+                                                         const double *f2, const double *u0, const double *u1,
+                                                         const double *u2, double *r0, double *r1, double *r2,
+                                                         double *partials) {
+  const DevGrid &g = M.g;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  double rr = 0.0;
+  if (i <= g.nx && j <= g.ny) {
+    const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
+    const double *pv[3] = {u0, u1, u2};
+    double yx, yy, yz;
+    node_apply<double>(M, i, j, k, n, pv, yx, yy, yz);
+    const double rx = f0[n] - yx, ry = f1[n] - yy, rzv = f2[n] - yz;
+    r0[n] = rx; r1[n] = ry; r2[n] = rzv;
+    rr = rx * rx + ry * ry + rzv * rzv;
+  }
+  const double s[1] = {rr};
+  const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  block_sums<1>(s, partials + b * kRedWidth);
+}
+
+__global__ __launch_bounds__(256) void residual_finalize(const double *part, int64_t nb, DevScalars *sc) {
+  __shared__ double out[1];
+  sum_partials<1>(part, nb, out);
+  if (threadIdx.x == 0) sc->rr = out[0];
+}
+
+__global__ void cast_kernel(const void *src, int src_f32, void *dst, int dst_f32, int64_t n) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
+    const double x = src_f32 ? double(((const float *)src)[t]) : ((const double *)src)[t];
+    if (dst_f32) ((float *)dst)[t] = float(x); else ((double *)dst)[t] = x;
+  }
+}
+
+__global__ void axpy64_kernel(double *y, const float *x, int64_t n) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+    y[t] += double(x[t]);
+}
+
+// Eq. (9) at the centroid: strain B(0) u_e (dN_a/dx = s_ax / (4 hx) there),
+// thermal strain cte * mean nodal rise, isotropic Hooke's law.
+__global__ __launch_bounds__(256) void von_mises_kernel(MechGrid M, const double *theta, const double *u0,
+                                                        const double *u1, const double *u2, double *vm) {
+  const DevGrid &g = M.g;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny || k >= g.nz) return;
+  const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
+  const double *row = g.mtab + g.mat[n] * kMatStride;
+  if (row[MC_VOID] != 0.0) { vm[n] = 0.0; return; }
+  const double qx = 0.25 * g.idx[i], qy = 0.25 * g.idy[j], qz = 0.25 * g.idz[k];
+  double exx = 0, eyy = 0, ezz = 0, gxy = 0, gyz = 0, gzx = 0, th = 0;
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+    const int64_t na = n + ax + ay * g.sy + az * g.sz;
+    const double dxa = (ax ? qx : -qx), dya = (ay ? qy : -qy), dza = (az ? qz : -qz);
+    const double ux = u0[na], uy = u1[na], uz = u2[na];
+    exx += dxa * ux; eyy += dya * uy; ezz += dza * uz;
+    gxy += dya * ux + dxa * uy;
+    gyz += dza * uy + dya * uz;
+    gzx += dxa * uz + dza * ux;
+    th += theta[na];
+  }
+  th *= 0.125;
+  const double et = row[MC_CTE] * th;
+  exx -= et; eyy -= et; ezz -= et;
+  const double lam = row[MC_LAMBDA], mu = row[MC_MU];
+  const double tr = lam * (exx + eyy + ezz);
+  const double sx = tr + 2 * mu * exx, sy = tr + 2 * mu * eyy, sz = tr + 2 * mu * ezz;
+  const double txy = mu * gxy, tyz = mu * gyz, tzx = mu * gzx;
+  const double a1 = sx - sy, a2 = sy - sz, a3 = sz - sx;
+  vm[n] = sqrt(0.5 * (a1 * a1 + a2 * a2 + a3 * a3 + 6.0 * (txy * txy + tyz * tyz + tzx * tzx)));
+}
+
+inline int flat_blocks(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024))); }
+
+}  // namespace
+
+hipError_t launch_mech_diag(const MechGrid &M, double *dinv[3], hipStream_t s) {
+  hipLaunchKernelGGL(mech_diag_kernel, node_grid(M.g), dim3(BX, BY), 0, s, M, dinv[0], dinv[1], dinv[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_mech_rhs(const MechGrid &M, const double *theta, double *f[3], double *partials,
+                           DevScalars *sc, double rtol, hipStream_t s) {
+  const dim3 grid = node_grid(M.g);
+  hipLaunchKernelGGL(mech_rhs_kernel, grid, dim3(BX, BY), 0, s, M, theta, f[0], f[1], f[2], partials);
+  hipLaunchKernelGGL(rhs_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
+                     int64_t(grid.x) * grid.y * grid.z, sc, rtol);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_setup(const MechGrid &M, const CgVecs<T> &v, const T *rhs[3], double *partials,
+                           DevScalars *sc, hipStream_t s) {
+  const dim3 grid = node_grid(M.g);
+  hipLaunchKernelGGL((cg_setup_kernel<T>), grid, dim3(BX, BY), 0, s, M, v, rhs[0], rhs[1], rhs[2], 0, partials);
+  hipLaunchKernelGGL(cg_setup_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
+                     int64_t(grid.x) * grid.y * grid.z, sc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_iteration(const MechGrid &M, const CgVecs<T> &v, double *partials, DevScalars *sc,
+                               hipStream_t s) {
+  const dim3 grid = node_grid(M.g);
+  const int64_t nb = int64_t(grid.x) * grid.y * grid.z;
+  hipLaunchKernelGGL((cg_apply_kernel<T>), grid, dim3(BX, BY), 0, s, M, v, (const DevScalars *)sc, partials);
+  hipLaunchKernelGGL(cg_alpha_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc);
+  const int fb = flat_blocks(M.g.ntot);
+  hipLaunchKernelGGL((cg_update_kernel<T>), dim3(fb), dim3(256), 0, s, v, M.g.ntot, (const DevScalars *)sc, partials);
+  hipLaunchKernelGGL(cg_beta_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, int64_t(fb), sc);
+  hipLaunchKernelGGL((cg_p_kernel<T>), dim3(fb), dim3(256), 0, s, v, M.g.ntot, (const DevScalars *)sc);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cg_setup<double>(const MechGrid &, const CgVecs<double> &, const double *[3], double *,
+                                            DevScalars *, hipStream_t);
+template hipError_t launch_cg_setup<float>(const MechGrid &, const CgVecs<float> &, const float *[3], double *,
+                                           DevScalars *, hipStream_t);
+template hipError_t launch_cg_iteration<double>(const MechGrid &, const CgVecs<double> &, double *, DevScalars *,
+                                                hipStream_t);
+template hipError_t launch_cg_iteration<float>(const MechGrid &, const CgVecs<float> &, double *, DevScalars *,
+                                               hipStream_t);
+
+hipError_t launch_residual64(const MechGrid &M, const double *f[3], const double *u[3], double *r[3],
+                             double *partials, DevScalars *sc, hipStream_t s) {
+  const dim3 grid = node_grid(M.g);
+  hipLaunchKernelGGL(residual64_kernel, grid, dim3(BX, BY), 0, s, M, f[0], f[1], f[2], u[0], u[1], u[2], r[0], r[1],
+                     r[2], partials);
+  hipLaunchKernelGGL(residual_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
+                     int64_t(grid.x) * grid.y * grid.z, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_cast(const void *src, int src_f32, void *dst, int dst_f32, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(cast_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, src, src_f32, dst, dst_f32, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_axpy64(double *y, const float *x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(axpy64_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, y, x, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_von_mises(const MechGrid &M, const double *theta, const double *u[3], double *vm, hipStream_t s) {
+  hipLaunchKernelGGL(von_mises_kernel, node_grid(M.g), dim3(BX, BY), 0, s, M, theta, u[0], u[1], u[2], vm);
+  return hipGetLastError();
+}
+
+}  // namespace etm

@@ -1,0 +1,984 @@
+// Host side of the C ABI declared in include/etm.h: input validation, derived
+// tables, DOF maps and constraints, workspace layout, the coupling schedule
+// of arXiv 2603.07038 Sec. II-A (EM step, Joule source, thermal step every R
+// EM steps) and the CG driver for Sec. II-B.  All GPU work goes through the
+// launchers in em.hip / mech.hip on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "etm_internal.h"
+
+using namespace etm;
+
+namespace {
+
+thread_local std::string g_err;
+
+etm_status fail(etm_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(ETM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct etm_plan {
+  // ---- inputs (deep copies)
+  int nx = 0, ny = 0, nz = 0, n_mat = 0;
+  std::vector<double> dx, dy, dz;
+  std::vector<uint8_t> mat_nat;
+  std::vector<etm_material> mats;
+  int n_waves = 0;
+  int64_t n_samples = 0;
+  std::vector<double> J;
+  etm_opts opts{};
+  double dt = 0;
+  int prec = ETM_PREC_FP64, R = 1;
+  // ---- layout
+  int64_t sy = 0, sz = 0, ntot = 0;
+  dim3 ngrid;
+  int64_t nblocks_node = 0;
+  // ---- host tables
+  std::vector<double> geo;  // dx,dy,dz,idx,idy,idz (n each), hx,hy,hz,ihx,ihy,ihz (n+1 each)
+  size_t geo_off[12] = {};
+  std::vector<double> mtab;
+  std::vector<uint8_t> mat_pad, flags, fixed;
+  std::vector<int64_t> pe_key;
+  std::vector<double> pe_gs, pw_wt;
+  std::vector<int32_t> pe_start, pw_wave;
+  std::vector<int64_t> probes_dev;  // [field, padded index]
+  int64_t hist_cap = 0;
+  int hist_cols = 4;
+  // ---- workspace regions
+  Region r_geo, r_mtab, r_mat, r_flags, r_fixed, r_pkey, r_pgs, r_pstart, r_pwave, r_pwt, r_J, r_probes;
+  Region r_e[3][3];     // FP64: three rotating e buffers;  MIXED: [0..1] e sets, [2] unused
+  Region r_d[2][3];     // MIXED: delta sets
+  Region r_theta[2], r_theta32, r_psum, r_part, r_sc, r_hist;
+  Region r_u64[3], r_f64[3], r_r64[3], r_p64[3], r_w64[3], r_dinv64[3];
+  Region r_u32[3], r_r32[3], r_p32[3], r_w32[3], r_dinv32[3], r_rhs32[3];
+  Region r_vm, r_stage;
+  size_t footprint = 0;
+  // ---- bound state
+  char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  DevScalars *sc_host = nullptr;  // pinned
+  int64_t step = 0;
+  int cur = 0;      // FP64: e^n = buffer cur; MIXED: set cur
+  int th_cur = 0;
+  int64_t rec = 0;
+  int64_t n_thermal = 0;
+  int n_solves = 0, cg_iters = 0, cg_outer = 0;
+  int64_t cg_total = 0;
+  double cg_relres = 0;
+  etm_status host_status = ETM_OK;
+  bool dinv_ready = false;
+
+  template <typename T>
+  T *ptr(const Region &r) const { return reinterpret_cast<T *>(ws + r.off); }
+
+  DevGrid dev_grid() const {
+    DevGrid g;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.n_mat = n_mat;
+    g.sy = sy; g.sz = sz; g.ntot = ntot;
+    const double *gb = ptr<double>(r_geo);
+    g.dx = gb + geo_off[0]; g.dy = gb + geo_off[1]; g.dz = gb + geo_off[2];
+    g.idx = gb + geo_off[3]; g.idy = gb + geo_off[4]; g.idz = gb + geo_off[5];
+    g.hx = gb + geo_off[6]; g.hy = gb + geo_off[7]; g.hz = gb + geo_off[8];
+    g.ihx = gb + geo_off[9]; g.ihy = gb + geo_off[10]; g.ihz = gb + geo_off[11];
+    g.mat = ptr<uint8_t>(r_mat);
+    g.flags = ptr<uint8_t>(r_flags);
+    g.mtab = ptr<double>(r_mtab);
+    int pec = 0;
+    for (int f = 0; f < 6; ++f) if (opts.em_bc[f] == ETM_PEC) pec |= 1 << f;
+    g.pec = pec;
+    return g;
+  }
+  DevPorts dev_ports() const {
+    DevPorts p;
+    p.n_edges = int(pe_key.size());
+    p.key = ptr<int64_t>(r_pkey);
+    p.gs = ptr<double>(r_pgs);
+    p.start = ptr<int32_t>(r_pstart);
+    p.wave = ptr<int32_t>(r_pwave);
+    p.wt = ptr<double>(r_pwt);
+    p.J = ptr<double>(r_J);
+    p.n_samples = n_samples;
+    return p;
+  }
+  MechGrid mech_grid() const {
+    MechGrid m;
+    m.g = dev_grid();
+    m.fixed = ptr<uint8_t>(r_fixed);
+    return m;
+  }
+  DevScalars *sc() const { return ptr<DevScalars>(r_sc); }
+  int64_t nidx(int i, int j, int k) const { return int64_t(k) * sz + int64_t(j) * sy + i; }
+};
+
+namespace {
+
+// Node-centred widths: half cells at the two ends.
+std::vector<double> dual(const std::vector<double> &d) {
+  std::vector<double> h(d.size() + 1, 0.0);
+  for (size_t i = 0; i < d.size(); ++i) { h[i] += 0.5 * d[i]; h[i + 1] += 0.5 * d[i]; }
+  return h;
+}
+
+double cfl_limit(const double *dx, int nx, const double *dy, int ny, const double *dz, int nz) {
+  double mx = 1e300, my = 1e300, mz = 1e300;
+  for (int i = 0; i < nx; ++i) mx = std::min(mx, dx[i]);
+  for (int j = 0; j < ny; ++j) my = std::min(my, dy[j]);
+  for (int k = 0; k < nz; ++k) mz = std::min(mz, dz[k]);
+  return 1.0 / (kC0 * std::sqrt(1.0 / (mx * mx) + 1.0 / (my * my) + 1.0 / (mz * mz)));
+}
+
+// Index of the node nearest the midpoint of a 1D node row (lower on a tie).
+int nearest_mid(const std::vector<double> &d) {
+  double tot = 0;
+  for (double v : d) tot += v;
+  const double mid = 0.5 * tot;
+  double x = 0, best = 1e300;
+  int bi = 0;
+  for (size_t i = 0; i <= d.size(); ++i) {
+    const double dist = std::fabs(x - mid);
+    if (dist < best) { best = dist; bi = int(i); }
+    if (i < d.size()) x += d[i];
+  }
+  return bi;
+}
+
+etm_status validate_and_copy(etm_plan *p, const etm_mesh *mesh, const etm_material *mats, int32_t n_mat,
+                             const etm_source *src, const etm_opts *opts) {
+  if (!mesh || !mats || !opts) return fail(ETM_E_INVAL, "null mesh, materials or options");
+  if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(ETM_E_INVAL, "mesh dimensions must be >= 1");
+  if ((int64_t)mesh->nx * mesh->ny * mesh->nz > (int64_t(1) << 34)) return fail(ETM_E_INVAL, "mesh too large");
+  if (!mesh->dx || !mesh->dy || !mesh->dz || !mesh->mat) return fail(ETM_E_INVAL, "null mesh array");
+  if (n_mat < 1 || n_mat > 256) return fail(ETM_E_INVAL, "n_mat must be in 1..256");
+  p->nx = mesh->nx; p->ny = mesh->ny; p->nz = mesh->nz; p->n_mat = n_mat;
+  p->dx.assign(mesh->dx, mesh->dx + p->nx);
+  p->dy.assign(mesh->dy, mesh->dy + p->ny);
+  p->dz.assign(mesh->dz, mesh->dz + p->nz);
+  for (auto *v : {&p->dx, &p->dy, &p->dz})
+    for (double w : *v)
+      if (!(w > 0.0) || !std::isfinite(w)) return fail(ETM_E_INVAL, "cell widths must be finite and > 0");
+  const size_t nc = size_t(p->nx) * p->ny * p->nz;
+  p->mat_nat.assign(mesh->mat, mesh->mat + nc);
+  for (size_t c = 0; c < nc; ++c)
+    if (p->mat_nat[c] >= n_mat) return fail(ETM_E_INVAL, "material id out of range at cell " + std::to_string(c));
+  p->mats.assign(mats, mats + n_mat);
+  for (int m = 0; m < n_mat; ++m) {
+    const etm_material &q = mats[m];
+    if (!(q.eps_r >= 1.0) || q.sigma0 < 0 || q.k < 0 || !(q.rho_cp > 0))
+      return fail(ETM_E_INVAL, "material " + std::to_string(m) + ": need eps_r >= 1, sigma0 >= 0, k >= 0, rho_cp > 0");
+    if (!q.is_void && (!(q.E > 0) || !(q.nu > -1.0 && q.nu < 0.5)))
+      return fail(ETM_E_INVAL, "material " + std::to_string(m) + ": need E > 0 and -1 < nu < 0.5");
+  }
+  p->opts = *opts;
+  if (opts->precision != ETM_PREC_FP64 && opts->precision != ETM_PREC_MIXED) return fail(ETM_E_INVAL, "bad precision");
+  for (int f = 0; f < 6; ++f)
+    if (opts->em_bc[f] != ETM_PMC && opts->em_bc[f] != ETM_PEC) return fail(ETM_E_INVAL, "bad em_bc");
+  if (opts->em_per_thermal < 1) return fail(ETM_E_INVAL, "em_per_thermal must be >= 1");
+  if (opts->mech_every_thermal < 0) return fail(ETM_E_INVAL, "mech_every_thermal must be >= 0");
+  if (opts->mech_bc != ETM_MECH_KINEMATIC && opts->mech_bc != ETM_MECH_CLAMP_ZMIN) return fail(ETM_E_INVAL, "bad mech_bc");
+  if (opts->cg_maxit < 1 || !(opts->cg_rtol > 0)) return fail(ETM_E_INVAL, "cg_maxit >= 1 and cg_rtol > 0 required");
+  if (opts->history_stride < 0 || opts->n_probes < 0 || (opts->n_probes > 0 && !opts->probes))
+    return fail(ETM_E_INVAL, "bad history options");
+  p->prec = opts->precision;
+  p->R = opts->em_per_thermal;
+  // time step
+  const double lim = cfl_limit(p->dx.data(), p->nx, p->dy.data(), p->ny, p->dz.data(), p->nz);
+  if (opts->dt > 0) {
+    p->dt = opts->dt;
+    if (p->dt > lim * (1.0 + 1e-12) && !opts->force_dt)
+      return fail(ETM_E_UNSTABLE, "dt " + std::to_string(p->dt) + " exceeds the CFL limit " + std::to_string(lim));
+  } else {
+    if (!(opts->cfl > 0 && opts->cfl <= 1.0)) return fail(ETM_E_INVAL, "cfl must be in (0, 1]");
+    p->dt = opts->cfl * lim;
+  }
+  // sources
+  p->n_waves = src ? src->n_waves : 0;
+  p->n_samples = src ? src->n_samples : 0;
+  if (src && src->n_ports > 0) {
+    if (!src->ports) return fail(ETM_E_INVAL, "null port array");
+    if (src->n_waves < 1 || src->n_samples < 1 || !src->J_half) return fail(ETM_E_INVAL, "ports need sampled waves");
+  }
+  if (p->n_waves > 0 && p->n_samples > 0) {
+    if (!src->J_half) return fail(ETM_E_INVAL, "null J_half");
+    p->J.assign(src->J_half, src->J_half + size_t(p->n_waves) * p->n_samples);
+  } else {
+    p->n_waves = 0;
+    p->n_samples = 0;
+  }
+  return ETM_OK;
+}
+
+etm_status derive(etm_plan *p, const etm_source *src) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  p->sy = ((nx + 1 + kPad - 1) / kPad) * kPad;
+  p->sz = p->sy * (ny + 1);
+  p->ntot = p->sz * (nz + 1);
+  p->ngrid = dim3((nx + 1 + 63) / 64, (ny + 1 + 3) / 4, nz + 1);
+  p->nblocks_node = int64_t(p->ngrid.x) * p->ngrid.y * p->ngrid.z;
+  // geometry table
+  const std::vector<double> hx = dual(p->dx), hy = dual(p->dy), hz = dual(p->dz);
+  const std::vector<double> *parts[12];
+  std::vector<double> idx(nx), idy(ny), idz(nz), ihx(nx + 1), ihy(ny + 1), ihz(nz + 1);
+  for (int i = 0; i < nx; ++i) idx[i] = 1.0 / p->dx[i];
+  for (int j = 0; j < ny; ++j) idy[j] = 1.0 / p->dy[j];
+  for (int k = 0; k < nz; ++k) idz[k] = 1.0 / p->dz[k];
+  for (int i = 0; i <= nx; ++i) ihx[i] = 1.0 / hx[i];
+  for (int j = 0; j <= ny; ++j) ihy[j] = 1.0 / hy[j];
+  for (int k = 0; k <= nz; ++k) ihz[k] = 1.0 / hz[k];
+  parts[0] = &p->dx; parts[1] = &p->dy; parts[2] = &p->dz;
+  parts[3] = &idx; parts[4] = &idy; parts[5] = &idz;
+  parts[6] = &hx; parts[7] = &hy; parts[8] = &hz;
+  parts[9] = &ihx; parts[10] = &ihy; parts[11] = &ihz;
+  p->geo.clear();
+  for (int q = 0; q < 12; ++q) {
+    p->geo_off[q] = p->geo.size();
+    p->geo.insert(p->geo.end(), parts[q]->begin(), parts[q]->end());
+  }
+  // material rows
+  p->mtab.assign(size_t(p->n_mat) * kMatStride, 0.0);
+  for (int m = 0; m < p->n_mat; ++m) {
+    const etm_material &q = p->mats[m];
+    double *row = &p->mtab[size_t(m) * kMatStride];
+    row[MC_EPSR] = q.eps_r;
+    row[MC_SIGS] = q.sigma0 * p->dt / (2.0 * kEps0);
+    row[MC_TCR] = q.tcr;
+    row[MC_K] = q.k;
+    row[MC_RHOCP] = q.rho_cp;
+    if (!q.is_void) {
+      const double lam = q.E * q.nu / ((1 + q.nu) * (1 - 2 * q.nu)), mu = q.E / (2 * (1 + q.nu));
+      row[MC_LAMBDA] = lam;
+      row[MC_MU] = mu;
+      row[MC_BETA] = (3 * lam + 2 * mu) * q.cte;
+      row[MC_CTE] = q.cte;
+    }
+    row[MC_VOID] = q.is_void ? 1.0 : 0.0;
+  }
+  // explicit thermal bound: forward Euler is stable when R dt lambda_max <= 2;
+  // Gershgorin with the per-cell mediant bound gives
+  // lambda_max <= 4 max_c (k/rho_cp)_c (1/dx^2 + 1/dy^2 + 1/dz^2)_min.
+  {
+    std::vector<char> used(p->n_mat, 0);
+    for (uint8_t m : p->mat_nat) used[m] = 1;
+    double dmax = 0;
+    for (int m = 0; m < p->n_mat; ++m) if (used[m]) dmax = std::max(dmax, p->mats[m].k / p->mats[m].rho_cp);
+    double mx = *std::min_element(p->dx.begin(), p->dx.end()), my = *std::min_element(p->dy.begin(), p->dy.end()),
+           mz = *std::min_element(p->dz.begin(), p->dz.end());
+    const double lam = 4.0 * dmax * (1 / (mx * mx) + 1 / (my * my) + 1 / (mz * mz));
+    if (p->R * p->dt * lam > 2.0 && !p->opts.force_dt)
+      return fail(ETM_E_UNSTABLE, "thermal step R*dt exceeds the forward-Euler bound");
+  }
+  // padded cell ids
+  p->mat_pad.assign(p->ntot, 0);
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      std::memcpy(&p->mat_pad[p->nidx(0, j, k)], &p->mat_nat[(size_t(k) * ny + j) * nx], nx);
+  // ports
+  p->flags.assign(p->ntot, 0);
+  p->pe_key.clear(); p->pe_gs.clear(); p->pe_start.clear(); p->pw_wave.clear(); p->pw_wt.clear();
+  if (src && src->n_ports > 0) {
+    struct PE { int64_t key; int wave; double wt, g; };
+    std::vector<PE> list;
+    list.reserve(size_t(src->n_ports));
+    for (int64_t q = 0; q < src->n_ports; ++q) {
+      const etm_port &pt = src->ports[q];
+      const int d = pt.dir;
+      if (d < 0 || d > 2) return fail(ETM_E_INVAL, "port " + std::to_string(q) + ": dir must be 0..2");
+      const int ni = nx + (d != 0), nj = ny + (d != 1), nk = nz + (d != 2);
+      if (pt.i < 0 || pt.i >= ni || pt.j < 0 || pt.j >= nj || pt.k < 0 || pt.k >= nk)
+        return fail(ETM_E_INVAL, "port " + std::to_string(q) + ": edge outside the mesh");
+      if (pt.wave < 0 || pt.wave >= p->n_waves) return fail(ETM_E_INVAL, "port " + std::to_string(q) + ": wave out of range");
+      if (!std::isfinite(pt.weight) || !(pt.g >= 0)) return fail(ETM_E_INVAL, "port " + std::to_string(q) + ": bad weight/g");
+      const int *b = p->opts.em_bc;
+      const bool pec = (d != 0 && ((pt.i == 0 && b[0]) || (pt.i == nx && b[1]))) ||
+                       (d != 1 && ((pt.j == 0 && b[2]) || (pt.j == ny && b[3]))) ||
+                       (d != 2 && ((pt.k == 0 && b[4]) || (pt.k == nz && b[5])));
+      if (pec) return fail(ETM_E_INVAL, "port " + std::to_string(q) + ": edge lies on a PEC face");
+      const int64_t node = p->nidx(pt.i, pt.j, pt.k);
+      list.push_back({int64_t(d) * p->ntot + node, pt.wave, pt.weight, pt.g});
+      p->flags[node] |= uint8_t(1 << d);
+    }
+    std::stable_sort(list.begin(), list.end(), [](const PE &a, const PE &b) { return a.key < b.key; });
+    for (size_t q = 0; q < list.size(); ++q) {
+      if (q == 0 || list[q].key != list[q - 1].key) {
+        p->pe_key.push_back(list[q].key);
+        p->pe_gs.push_back(0.0);
+        p->pe_start.push_back(int32_t(p->pw_wave.size()));
+      }
+      p->pe_gs.back() += list[q].g * p->dt / (2.0 * kEps0);
+      p->pw_wave.push_back(list[q].wave);
+      p->pw_wt.push_back(list[q].wt * p->dt / kEps0);
+    }
+    p->pe_start.push_back(int32_t(p->pw_wave.size()));
+  } else {
+    p->pe_start.push_back(0);
+  }
+  // mechanical constraints
+  p->fixed.assign(p->ntot, 0);
+  std::vector<uint8_t> solid(p->ntot, 0);
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        if (p->mats[p->mat_nat[(size_t(k) * ny + j) * nx + i]].is_void) continue;
+        for (int c = 0; c < 8; ++c) solid[p->nidx(i + (c & 1), j + ((c >> 1) & 1), k + (c >> 2))] = 1;
+      }
+  for (int k = 0; k <= nz; ++k)
+    for (int j = 0; j <= ny; ++j)
+      for (int i = 0; i <= nx; ++i) {
+        const int64_t n = p->nidx(i, j, k);
+        p->fixed[n] = solid[n] ? 0 : 7;
+      }
+  if (p->opts.mech_mask) {
+    for (int k = 0; k <= nz; ++k)
+      for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i)
+          p->fixed[p->nidx(i, j, k)] |= p->opts.mech_mask[(size_t(k) * (ny + 1) + j) * (nx + 1) + i] & 7;
+  } else if (p->opts.mech_bc == ETM_MECH_CLAMP_ZMIN) {
+    for (int j = 0; j <= ny; ++j)
+      for (int i = 0; i <= nx; ++i) p->fixed[p->nidx(i, j, 0)] = 7;
+  } else {
+    const int ic = nearest_mid(p->dx), jc = nearest_mid(p->dy);
+    p->fixed[p->nidx(ic, jc, 0)] |= 7;
+    p->fixed[p->nidx(nx, jc, 0)] |= 6;
+    p->fixed[p->nidx(ic, ny, 0)] |= 4;
+  }
+  // probes
+  p->probes_dev.clear();
+  for (int q = 0; q < p->opts.n_probes; ++q) {
+    const int64_t *pr = p->opts.probes + 4 * q;
+    const int f = int(pr[0]);
+    const int64_t i = pr[1], j = pr[2], k = pr[3];
+    if (f < 0 || f > 3) return fail(ETM_E_INVAL, "probe field must be 0..3");
+    const int ni = nx + (f != 0), nj = ny + (f != 1), nk = nz + (f != 2);
+    if (i < 0 || j < 0 || k < 0 || i >= ni || j >= nj || k >= nk) return fail(ETM_E_INVAL, "probe outside the mesh");
+    p->probes_dev.push_back(f);
+    p->probes_dev.push_back(p->nidx(int(i), int(j), int(k)));
+  }
+  p->hist_cols = 4 + p->opts.n_probes;
+  if (p->opts.history_stride > 0) {
+    p->hist_cap = p->opts.history_cap > 0 ? p->opts.history_cap
+                                          : std::max<int64_t>(1, p->opts.n_em_steps_hint / p->opts.history_stride + 1);
+  } else {
+    p->hist_cap = 0;
+  }
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](Region &r, size_t bytes) { r.off = off; r.bytes = align256(std::max<size_t>(bytes, 1)); off += r.bytes; };
+  const size_t N = size_t(p->ntot);
+  take(p->r_geo, p->geo.size() * 8);
+  take(p->r_mtab, p->mtab.size() * 8);
+  take(p->r_mat, N);
+  take(p->r_flags, N);
+  take(p->r_fixed, N);
+  take(p->r_pkey, p->pe_key.size() * 8);
+  take(p->r_pgs, p->pe_gs.size() * 8);
+  take(p->r_pstart, p->pe_start.size() * 4);
+  take(p->r_pwave, p->pw_wave.size() * 4);
+  take(p->r_pwt, p->pw_wt.size() * 8);
+  take(p->r_J, p->J.size() * 8);
+  take(p->r_probes, p->probes_dev.size() * 8);
+  if (p->prec == ETM_PREC_FP64) {
+    for (int b = 0; b < 3; ++b) for (int c = 0; c < 3; ++c) take(p->r_e[b][c], N * 8);
+  } else {
+    for (int b = 0; b < 2; ++b) for (int c = 0; c < 3; ++c) take(p->r_e[b][c], N * 4);
+    for (int b = 0; b < 2; ++b) for (int c = 0; c < 3; ++c) take(p->r_d[b][c], N * 4);
+    take(p->r_theta32, N * 4);
+  }
+  take(p->r_theta[0], N * 8);
+  take(p->r_theta[1], N * 8);
+  take(p->r_psum, N * 8);
+  take(p->r_part, size_t(std::max<int64_t>(p->nblocks_node, 1024)) * kRedWidth * 8);
+  take(p->r_sc, sizeof(DevScalars));
+  take(p->r_hist, size_t(p->hist_cap) * p->hist_cols * 8);
+  for (int c = 0; c < 3; ++c) {
+    take(p->r_u64[c], N * 8); take(p->r_f64[c], N * 8); take(p->r_r64[c], N * 8); take(p->r_dinv64[c], N * 8);
+  }
+  if (p->prec == ETM_PREC_FP64) {
+    for (int c = 0; c < 3; ++c) { take(p->r_p64[c], N * 8); take(p->r_w64[c], N * 8); }
+  } else {
+    for (int c = 0; c < 3; ++c) {
+      take(p->r_u32[c], N * 4); take(p->r_r32[c], N * 4); take(p->r_p32[c], N * 4);
+      take(p->r_w32[c], N * 4); take(p->r_dinv32[c], N * 4); take(p->r_rhs32[c], N * 4);
+    }
+  }
+  take(p->r_vm, N * 8);
+  take(p->r_stage, N * 8);
+  p->footprint = off;
+  return ETM_OK;
+}
+
+struct FieldDesc {
+  int ni, nj, nk;
+};
+
+FieldDesc field_shape(const etm_plan *p, int field) {
+  switch (field) {
+    case ETM_FIELD_EX: case ETM_FIELD_EX_PREV: return {p->nx, p->ny + 1, p->nz + 1};
+    case ETM_FIELD_EY: case ETM_FIELD_EY_PREV: return {p->nx + 1, p->ny, p->nz + 1};
+    case ETM_FIELD_EZ: case ETM_FIELD_EZ_PREV: return {p->nx + 1, p->ny + 1, p->nz};
+    case ETM_FIELD_VM: return {p->nx, p->ny, p->nz};
+    default: return {p->nx + 1, p->ny + 1, p->nz + 1};
+  }
+}
+
+// Pointer and element type of a state field on the device.
+const void *field_ptr(const etm_plan *p, int field, int *is_f32) {
+  *is_f32 = 0;
+  const bool mixed = p->prec == ETM_PREC_MIXED;
+  switch (field) {
+    case ETM_FIELD_EX: case ETM_FIELD_EY: case ETM_FIELD_EZ:
+      *is_f32 = mixed;
+      return p->ws + p->r_e[p->cur][field - ETM_FIELD_EX].off;
+    case ETM_FIELD_EX_PREV: case ETM_FIELD_EY_PREV: case ETM_FIELD_EZ_PREV:
+      if (mixed) { *is_f32 = 1; return p->ws + p->r_d[p->cur][field - ETM_FIELD_EX_PREV].off; }
+      return p->ws + p->r_e[(p->cur + 2) % 3][field - ETM_FIELD_EX_PREV].off;
+    case ETM_FIELD_THETA: return p->ws + p->r_theta[p->th_cur].off;
+    case ETM_FIELD_PSUM: return p->ws + p->r_psum.off;
+    case ETM_FIELD_UX: case ETM_FIELD_UY: case ETM_FIELD_UZ: return p->ws + p->r_u64[field - ETM_FIELD_UX].off;
+    case ETM_FIELD_VM: return p->ws + p->r_vm.off;
+    case ETM_FIELD_FX: case ETM_FIELD_FY: case ETM_FIELD_FZ: return p->ws + p->r_f64[field - ETM_FIELD_FX].off;
+  }
+  return nullptr;
+}
+
+etm_status em_one_step(etm_plan *p) {
+  EmLaunch L;
+  L.g = p->dev_grid();
+  L.ports = p->dev_ports();
+  L.precision = p->prec;
+  L.c2dt2 = (kC0 * p->dt) * (kC0 * p->dt);
+  L.jf = kEps0 / p->dt;
+  L.step = p->step;
+  L.theta = p->ptr<double>(p->r_theta[p->th_cur]);
+  L.theta32 = p->prec == ETM_PREC_MIXED ? p->ptr<float>(p->r_theta32) : nullptr;
+  L.psum = p->ptr<double>(p->r_psum);
+  if (p->prec == ETM_PREC_FP64) {
+    const int c = p->cur, prv = (c + 2) % 3, nxt = (c + 1) % 3;
+    for (int d = 0; d < 3; ++d) {
+      L.e0[d] = p->ws + p->r_e[c][d].off;
+      L.e1[d] = p->ws + p->r_e[prv][d].off;
+      L.out0[d] = p->ws + p->r_e[nxt][d].off;
+      L.out1[d] = nullptr;
+    }
+  } else {
+    const int s = p->cur, o = 1 - s;
+    for (int d = 0; d < 3; ++d) {
+      L.e0[d] = p->ws + p->r_e[s][d].off;
+      L.e1[d] = p->ws + p->r_d[s][d].off;
+      L.out0[d] = p->ws + p->r_e[o][d].off;
+      L.out1[d] = p->ws + p->r_d[o][d].off;
+    }
+  }
+  HIP_TRY(launch_em_step(L, p->stream));
+  return ETM_OK;
+}
+
+etm_status diag_record(etm_plan *p, int old_cur) {
+  // after the step: new state is p->cur, old is old_cur
+  DiagLaunch D;
+  D.g = p->dev_grid();
+  D.precision = p->prec;
+  D.c2dt2 = (kC0 * p->dt) * (kC0 * p->dt);
+  D.dt = p->dt;
+  for (int d = 0; d < 3; ++d) {
+    D.e_new[d] = p->ws + p->r_e[p->cur][d].off;
+    D.e_old[d] = p->prec == ETM_PREC_FP64 ? (const void *)(p->ws + p->r_e[old_cur][d].off)
+                                          : (const void *)(p->ws + p->r_d[p->cur][d].off);
+  }
+  D.theta = p->ptr<double>(p->r_theta[p->th_cur]);
+  D.psum = p->ptr<double>(p->r_psum);
+  D.partials = p->ptr<double>(p->r_part);
+  D.sc = p->sc();
+  D.hist_row = p->ptr<double>(p->r_hist) + std::min(p->rec, std::max<int64_t>(p->hist_cap - 1, 0)) * p->hist_cols;
+  D.n_probes = p->opts.n_probes;
+  D.probes = p->ptr<int64_t>(p->r_probes);
+  D.step = p->step;
+  D.cap = p->hist_cap;
+  D.rec = p->rec;
+  HIP_TRY(launch_diag(D, p->stream));
+  if (p->rec < p->hist_cap) p->rec++;
+  return ETM_OK;
+}
+
+etm_status thermal_one(etm_plan *p) {
+  ThermalLaunch T;
+  T.g = p->dev_grid();
+  T.dt = p->dt;
+  T.R = p->R;
+  T.theta_in = p->ptr<double>(p->r_theta[p->th_cur]);
+  T.theta_out = p->ptr<double>(p->r_theta[1 - p->th_cur]);
+  T.theta32 = p->prec == ETM_PREC_MIXED ? p->ptr<float>(p->r_theta32) : nullptr;
+  T.psum = p->ptr<double>(p->r_psum);
+  T.partials = p->ptr<double>(p->r_part);
+  T.sc = p->sc();
+  HIP_TRY(launch_thermal(T, p->stream));
+  p->th_cur = 1 - p->th_cur;
+  p->n_thermal++;
+  return ETM_OK;
+}
+
+etm_status poll_scalars(etm_plan *p) {
+  HIP_TRY(hipMemcpyAsync(p->sc_host, p->sc(), sizeof(DevScalars), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return ETM_OK;
+}
+
+etm_status set_tol2(etm_plan *p, double tol2) {
+  p->sc_host->tol2 = tol2;
+  HIP_TRY(hipMemcpyAsync(&p->sc()->tol2, &p->sc_host->tol2, sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return ETM_OK;
+}
+
+template <typename T>
+etm_status run_cg(etm_plan *p, const MechGrid &M, const CgVecs<T> &v, const T *rhs[3], int zero_init, int budget,
+                  int *iters) {
+  etm_status st;
+  (void)zero_init;
+  HIP_TRY(launch_cg_setup<T>(M, v, rhs, p->ptr<double>(p->r_part), p->sc(), p->stream));
+  *iters = 0;
+  const int chunk = 32;
+  for (;;) {
+    if ((st = poll_scalars(p)) != ETM_OK) return st;
+    *iters = p->sc_host->iters;
+    if (p->sc_host->done || *iters >= budget) break;
+    const int n = std::min(chunk, budget - *iters);
+    for (int q = 0; q < n; ++q) HIP_TRY(launch_cg_iteration<T>(M, v, p->ptr<double>(p->r_part), p->sc(), p->stream));
+  }
+  return ETM_OK;
+}
+
+etm_status mech_solve_impl(etm_plan *p) {
+  etm_status st;
+  const MechGrid M = p->mech_grid();
+  const int64_t N = p->ntot;
+  double *u64[3], *f64[3], *r64[3], *dinv64[3];
+  for (int c = 0; c < 3; ++c) {
+    u64[c] = p->ptr<double>(p->r_u64[c]); f64[c] = p->ptr<double>(p->r_f64[c]);
+    r64[c] = p->ptr<double>(p->r_r64[c]); dinv64[c] = p->ptr<double>(p->r_dinv64[c]);
+  }
+  if (!p->dinv_ready) {
+    HIP_TRY(launch_mech_diag(M, dinv64, p->stream));
+    if (p->prec == ETM_PREC_MIXED)
+      for (int c = 0; c < 3; ++c) HIP_TRY(launch_vec_cast(dinv64[c], 0, p->ptr<float>(p->r_dinv32[c]), 1, N, p->stream));
+    p->dinv_ready = true;
+  }
+  const double *theta = p->ptr<double>(p->r_theta[p->th_cur]);
+  HIP_TRY(launch_mech_rhs(M, theta, f64, p->ptr<double>(p->r_part), p->sc(), p->opts.cg_rtol, p->stream));
+  if ((st = poll_scalars(p)) != ETM_OK) return st;
+  const double fn2 = p->sc_host->fnorm2, target2 = p->opts.cg_rtol * p->opts.cg_rtol * fn2;
+  const int maxit = p->opts.cg_maxit;
+  int total = 0, outer = 0;
+  double rr = 0;
+  bool conv = false;
+  const double *cf64[3] = {f64[0], f64[1], f64[2]};
+  const double *cu64[3] = {u64[0], u64[1], u64[2]};
+  if (fn2 == 0.0) {
+    for (int c = 0; c < 3; ++c) HIP_TRY(launch_fill(u64[c], N * 8, p->stream));
+    conv = true;
+  } else if (p->prec == ETM_PREC_FP64) {
+    CgVecs<double> v;
+    for (int c = 0; c < 3; ++c) {
+      v.u[c] = u64[c]; v.r[c] = r64[c]; v.p[c] = p->ptr<double>(p->r_p64[c]); v.w[c] = p->ptr<double>(p->r_w64[c]);
+      v.dinv[c] = dinv64[c];
+    }
+    while (total < maxit) {
+      if ((st = set_tol2(p, target2)) != ETM_OK) return st;
+      int it = 0;
+      if ((st = run_cg<double>(p, M, v, cf64, 0, maxit - total, &it)) != ETM_OK) return st;
+      total += it;
+      // true residual
+      HIP_TRY(launch_residual64(M, cf64, cu64, r64, p->ptr<double>(p->r_part), p->sc(), p->stream));
+      ++outer;
+      if ((st = poll_scalars(p)) != ETM_OK) return st;
+      rr = p->sc_host->rr;
+      if (rr <= target2) { conv = true; break; }
+      if (it == 0) break;
+    }
+  } else {
+    // iterative refinement: FP64 residual, FP32 Jacobi-PCG correction
+    CgVecs<float> v;
+    const float *rhs32[3];
+    for (int c = 0; c < 3; ++c) {
+      v.u[c] = p->ptr<float>(p->r_u32[c]); v.r[c] = p->ptr<float>(p->r_r32[c]); v.p[c] = p->ptr<float>(p->r_p32[c]);
+      v.w[c] = p->ptr<float>(p->r_w32[c]); v.dinv[c] = p->ptr<float>(p->r_dinv32[c]);
+      rhs32[c] = p->ptr<float>(p->r_rhs32[c]);
+    }
+    const double inner_rtol = 1e-4;
+    for (outer = 0; outer < 50;) {
+      HIP_TRY(launch_residual64(M, cf64, cu64, r64, p->ptr<double>(p->r_part), p->sc(), p->stream));
+      ++outer;
+      if ((st = poll_scalars(p)) != ETM_OK) return st;
+      rr = p->sc_host->rr;
+      if (rr <= target2) { conv = true; break; }
+      if (total >= maxit) break;
+      for (int c = 0; c < 3; ++c) {
+        HIP_TRY(launch_vec_cast(r64[c], 0, (void *)rhs32[c], 1, N, p->stream));
+        HIP_TRY(launch_fill(v.u[c], N * 4, p->stream));
+      }
+      if ((st = set_tol2(p, std::max(inner_rtol * inner_rtol * rr, 0.25 * target2))) != ETM_OK) return st;
+      int it = 0;
+      if ((st = run_cg<float>(p, M, v, rhs32, 1, maxit - total, &it)) != ETM_OK) return st;
+      total += it;
+      for (int c = 0; c < 3; ++c) HIP_TRY(launch_vec_axpy64(u64[c], v.u[c], N, p->stream));
+      if (it == 0) break;
+    }
+  }
+  HIP_TRY(launch_von_mises(M, theta, cu64, p->ptr<double>(p->r_vm), p->stream));
+  p->cg_iters = total;
+  p->cg_outer = outer;
+  p->cg_total += total;
+  p->cg_relres = fn2 > 0 ? std::sqrt(rr / fn2) : 0.0;
+  p->n_solves++;
+  if (!conv) {
+    if (p->host_status == ETM_OK) p->host_status = ETM_E_NOCONV;
+    return fail(ETM_E_NOCONV, "mechanical CG did not converge: relres " + std::to_string(p->cg_relres) + " after " +
+                                  std::to_string(total) + " iterations");
+  }
+  return ETM_OK;
+}
+
+}  // namespace
+
+// =============================== C ABI ======================================
+extern "C" {
+
+etm_status etm_opts_default(etm_opts *o) {
+  if (!o) return fail(ETM_E_INVAL, "null opts");
+  std::memset(o, 0, sizeof(*o));
+  o->dt = 0.0;
+  o->cfl = 0.9;
+  o->precision = ETM_PREC_FP64;
+  o->em_per_thermal = 1;
+  o->mech_every_thermal = 0;
+  o->mech_bc = ETM_MECH_KINEMATIC;
+  o->cg_maxit = 200000;
+  o->cg_rtol = 1e-8;
+  return ETM_OK;
+}
+
+etm_status etm_cfl_dt(const etm_mesh *mesh, double cfl, double *dt) {
+  if (!mesh || !dt || !mesh->dx || !mesh->dy || !mesh->dz || mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1)
+    return fail(ETM_E_INVAL, "bad mesh");
+  if (!(cfl > 0)) return fail(ETM_E_INVAL, "cfl must be > 0");
+  *dt = cfl * cfl_limit(mesh->dx, mesh->nx, mesh->dy, mesh->ny, mesh->dz, mesh->nz);
+  return ETM_OK;
+}
+
+etm_status etm_plan_create(const etm_mesh *mesh, const etm_material *mats, int32_t n_mat, const etm_source *src,
+                           const etm_opts *opts, etm_plan **out) {
+  if (!out) return fail(ETM_E_INVAL, "null out");
+  *out = nullptr;
+  etm_plan *p = nullptr;
+  try {
+    p = new etm_plan();
+    etm_status st = validate_and_copy(p, mesh, mats, n_mat, src, opts);
+    if (st == ETM_OK) st = derive(p, src);
+    if (st != ETM_OK) { delete p; return st; }
+    p->opts.mech_mask = nullptr;  // copied into p->fixed
+    p->opts.probes = nullptr;     // copied into probes_dev
+  } catch (const std::bad_alloc &) {
+    delete p;
+    return fail(ETM_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    delete p;
+    return fail(ETM_E_INVAL, "unexpected error in plan creation");
+  }
+  *out = p;
+  return ETM_OK;
+}
+
+etm_status etm_plan_footprint(const etm_plan *p, size_t *bytes) {
+  if (!p || !bytes) return fail(ETM_E_INVAL, "null argument");
+  *bytes = p->footprint;
+  return ETM_OK;
+}
+
+etm_status etm_plan_dt(const etm_plan *p, double *dt) {
+  if (!p || !dt) return fail(ETM_E_INVAL, "null argument");
+  *dt = p->dt;
+  return ETM_OK;
+}
+
+etm_status etm_plan_dofs(const etm_plan *p, int64_t *em, int64_t *thermal, int64_t *mech) {
+  if (!p) return fail(ETM_E_INVAL, "null plan");
+  const int64_t nx = p->nx, ny = p->ny, nz = p->nz;
+  const int64_t nodes = (nx + 1) * (ny + 1) * (nz + 1);
+  if (em) *em = nx * (ny + 1) * (nz + 1) + (nx + 1) * ny * (nz + 1) + (nx + 1) * (ny + 1) * nz;
+  if (thermal) *thermal = nodes;
+  if (mech) *mech = 3 * nodes;
+  return ETM_OK;
+}
+
+etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
+  if (!p || !ws) return fail(ETM_E_INVAL, "null plan or workspace");
+  if (bytes < p->footprint) return fail(ETM_E_NOMEM, "workspace smaller than the footprint");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(ETM_E_INVAL, "workspace must be 256-byte aligned");
+  p->ws = static_cast<char *>(ws);
+  p->stream = static_cast<hipStream_t>(stream);
+  if (!p->sc_host) HIP_TRY(hipHostMalloc((void **)&p->sc_host, sizeof(DevScalars), hipHostMallocDefault));
+  std::memset(p->sc_host, 0, sizeof(DevScalars));
+  HIP_TRY(launch_fill(p->ws, int64_t(p->footprint), p->stream));
+  auto up = [&](const Region &r, const void *src, size_t n) -> etm_status {
+    if (n) HIP_TRY(hipMemcpyAsync(p->ws + r.off, src, n, hipMemcpyHostToDevice, p->stream));
+    return ETM_OK;
+  };
+  etm_status st;
+  if ((st = up(p->r_geo, p->geo.data(), p->geo.size() * 8)) ||
+      (st = up(p->r_mtab, p->mtab.data(), p->mtab.size() * 8)) ||
+      (st = up(p->r_mat, p->mat_pad.data(), p->mat_pad.size())) ||
+      (st = up(p->r_flags, p->flags.data(), p->flags.size())) ||
+      (st = up(p->r_fixed, p->fixed.data(), p->fixed.size())) ||
+      (st = up(p->r_pkey, p->pe_key.data(), p->pe_key.size() * 8)) ||
+      (st = up(p->r_pgs, p->pe_gs.data(), p->pe_gs.size() * 8)) ||
+      (st = up(p->r_pstart, p->pe_start.data(), p->pe_start.size() * 4)) ||
+      (st = up(p->r_pwave, p->pw_wave.data(), p->pw_wave.size() * 4)) ||
+      (st = up(p->r_pwt, p->pw_wt.data(), p->pw_wt.size() * 8)) ||
+      (st = up(p->r_J, p->J.data(), p->J.size() * 8)) ||
+      (st = up(p->r_probes, p->probes_dev.data(), p->probes_dev.size() * 8)))
+    return st;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->bound = true;
+  p->step = 0; p->cur = 0; p->th_cur = 0; p->rec = 0; p->n_thermal = 0;
+  p->n_solves = 0; p->cg_iters = 0; p->cg_outer = 0; p->cg_total = 0; p->cg_relres = 0;
+  p->host_status = ETM_OK;
+  p->dinv_ready = false;
+  return ETM_OK;
+}
+
+etm_status etm_advance(etm_plan *p, int64_t n) {
+  if (!p) return fail(ETM_E_INVAL, "null plan");
+  if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  if (n < 0) return fail(ETM_E_INVAL, "negative step count");
+  etm_status st;
+  for (int64_t q = 0; q < n; ++q) {
+    const int old = p->cur;
+    if ((st = em_one_step(p)) != ETM_OK) return st;
+    p->cur = p->prec == ETM_PREC_FP64 ? (p->cur + 1) % 3 : 1 - p->cur;
+    p->step++;
+    if (p->step % p->R == 0) {
+      if ((st = thermal_one(p)) != ETM_OK) return st;
+      if (p->opts.mech_every_thermal > 0 && p->n_thermal % p->opts.mech_every_thermal == 0) {
+        st = mech_solve_impl(p);
+        if (st != ETM_OK && st != ETM_E_NOCONV) return st;
+      }
+    }
+    if (p->opts.history_stride > 0 && p->step % p->opts.history_stride == 0)
+      if ((st = diag_record(p, old)) != ETM_OK) return st;
+  }
+  return ETM_OK;
+}
+
+etm_status etm_mech_solve(etm_plan *p) {
+  if (!p) return fail(ETM_E_INVAL, "null plan");
+  if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  return mech_solve_impl(p);
+}
+
+etm_status etm_sync(etm_plan *p, etm_run_info *info) {
+  if (!p) return fail(ETM_E_INVAL, "null plan");
+  if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  etm_status st = poll_scalars(p);
+  if (st != ETM_OK) return st;
+  const DevScalars &s = *p->sc_host;
+  if (info) {
+    info->step = p->step;
+    info->status = p->host_status != ETM_OK ? p->host_status : s.status;
+    info->cg_iters = p->cg_iters;
+    info->cg_outer = p->cg_outer;
+    info->n_solves = p->n_solves;
+    info->cg_relres = p->cg_relres;
+    info->theta_max = s.theta_max;
+    info->ejoule = s.ejoule;
+    info->n_records = p->rec;
+    info->cg_iters_total = p->cg_total;
+  }
+  if (s.status != ETM_OK) return fail(s.status, "non-finite field detected on the device");
+  if (p->host_status != ETM_OK) return fail(p->host_status, "mechanical solve did not converge");
+  return ETM_OK;
+}
+
+etm_status etm_read(const etm_plan *p, int32_t field, void *dst, size_t bytes, int32_t dst_is_device) {
+  if (!p || !dst) return fail(ETM_E_INVAL, "null argument");
+  if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  if (field < ETM_FIELD_EX || field > ETM_FIELD_FZ) return fail(ETM_E_INVAL, "unknown field");
+  const FieldDesc fd = field_shape(p, field);
+  const size_t need = size_t(fd.ni) * fd.nj * fd.nk * 8;
+  if (bytes != need) return fail(ETM_E_INVAL, "dst size " + std::to_string(bytes) + " != " + std::to_string(need));
+  const bool mixed_prev = p->prec == ETM_PREC_MIXED && field >= ETM_FIELD_EX_PREV && field <= ETM_FIELD_EZ_PREV;
+  if (mixed_prev && dst_is_device) return fail(ETM_E_INVAL, "e^{n-1} of the mixed path is read to host memory only");
+  int f32 = 0;
+  const void *src = field_ptr(p, field, &f32);
+  double *stage = p->ptr<double>(p->r_stage);
+  HIP_TRY(launch_pack(src, f32, p->sy, p->sz, fd.ni, fd.nj, fd.nk, dst_is_device ? (double *)dst : stage, p->stream));
+  if (!dst_is_device) {
+    HIP_TRY(hipMemcpyAsync(dst, stage, need, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    if (mixed_prev) {  // e^{n-1} = e^n - delta^{n-1/2}
+      std::vector<double> e(need / 8);
+      const void *esrc = field_ptr(p, field - ETM_FIELD_EX_PREV, &f32);
+      HIP_TRY(launch_pack(esrc, f32, p->sy, p->sz, fd.ni, fd.nj, fd.nk, stage, p->stream));
+      HIP_TRY(hipMemcpyAsync(e.data(), stage, need, hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      double *d = static_cast<double *>(dst);
+      for (size_t q = 0; q < e.size(); ++q) d[q] = e[q] - d[q];
+    }
+  }
+  return ETM_OK;
+}
+
+etm_status etm_write(etm_plan *p, int32_t field, const void *src, size_t bytes, int32_t src_is_device) {
+  if (!p || !src) return fail(ETM_E_INVAL, "null argument");
+  if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  if (field < ETM_FIELD_EX || field > ETM_FIELD_UZ || field == ETM_FIELD_VM)
+    return fail(ETM_E_INVAL, "field is not writable");
+  const FieldDesc fd = field_shape(p, field);
+  const size_t need = size_t(fd.ni) * fd.nj * fd.nk * 8;
+  if (bytes != need) return fail(ETM_E_INVAL, "src size mismatch");
+  double *stage = p->ptr<double>(p->r_stage);
+  std::vector<double> tmp;
+  const void *from = src;
+  const bool mixed_prev = p->prec == ETM_PREC_MIXED && field >= ETM_FIELD_EX_PREV && field <= ETM_FIELD_EZ_PREV;
+  if (mixed_prev) {  // store delta^{n-1/2} = e^n - e^{n-1}
+    if (src_is_device) return fail(ETM_E_INVAL, "e^{n-1} of the mixed path is written from host memory only");
+    tmp.resize(need / 8);
+    etm_status st = etm_read(p, field - ETM_FIELD_EX_PREV, tmp.data(), need, 0);
+    if (st != ETM_OK) return st;
+    const double *s = static_cast<const double *>(src);
+    for (size_t q = 0; q < tmp.size(); ++q) tmp[q] -= s[q];
+    from = tmp.data();
+  }
+  if (src_is_device) {
+    HIP_TRY(hipMemcpyAsync(stage, from, need, hipMemcpyDeviceToDevice, p->stream));
+  } else {
+    HIP_TRY(hipMemcpyAsync(stage, from, need, hipMemcpyHostToDevice, p->stream));
+  }
+  int f32 = 0;
+  void *dstp = const_cast<void *>(field_ptr(p, field, &f32));
+  HIP_TRY(launch_unpack(stage, fd.ni, fd.nj, fd.nk, dstp, f32, p->sy, p->sz, p->stream));
+  if (field == ETM_FIELD_THETA && p->prec == ETM_PREC_MIXED)
+    HIP_TRY(launch_unpack(stage, fd.ni, fd.nj, fd.nk, p->ptr<float>(p->r_theta32), 1, p->sy, p->sz, p->stream));
+  if (field >= ETM_FIELD_UX && field <= ETM_FIELD_UZ) {
+    // keep fixed DOFs at zero
+    std::vector<double> h(need / 8);
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return ETM_OK;
+}
+
+etm_status etm_read_history(const etm_plan *p, double *dst, size_t bytes, int64_t *n_rows) {
+  if (!p || (!dst && bytes)) return fail(ETM_E_INVAL, "null argument");
+  if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  const size_t row = size_t(p->hist_cols) * 8;
+  const int64_t rows = std::min<int64_t>(p->rec, int64_t(bytes / row));
+  if (rows > 0) {
+    HIP_TRY(hipMemcpyAsync(dst, p->ptr<double>(p->r_hist), size_t(rows) * row, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  if (n_rows) *n_rows = rows;
+  return ETM_OK;
+}
+
+namespace {
+struct CkptHeader {
+  uint64_t magic;
+  int64_t step, rec, n_thermal, cg_total;
+  int32_t cur, th_cur, prec, n_solves;
+  int64_t ntot;
+};
+constexpr uint64_t kMagic = 0x45544d434b505431ull;
+
+std::vector<const Region *> state_regions(const etm_plan *p) {
+  std::vector<const Region *> r;
+  for (int b = 0; b < 3; ++b) for (int c = 0; c < 3; ++c) if (p->r_e[b][c].bytes) r.push_back(&p->r_e[b][c]);
+  if (p->prec == ETM_PREC_MIXED) {
+    for (int b = 0; b < 2; ++b) for (int c = 0; c < 3; ++c) r.push_back(&p->r_d[b][c]);
+    r.push_back(&p->r_theta32);
+  }
+  r.push_back(&p->r_theta[0]);
+  r.push_back(&p->r_theta[1]);
+  r.push_back(&p->r_psum);
+  r.push_back(&p->r_sc);
+  r.push_back(&p->r_hist);
+  for (int c = 0; c < 3; ++c) r.push_back(&p->r_u64[c]);
+  return r;
+}
+}  // namespace
+
+etm_status etm_checkpoint_size(const etm_plan *p, size_t *bytes) {
+  if (!p || !bytes) return fail(ETM_E_INVAL, "null argument");
+  size_t s = sizeof(CkptHeader);
+  for (const Region *r : state_regions(p)) s += r->bytes;
+  *bytes = s;
+  return ETM_OK;
+}
+
+etm_status etm_checkpoint(const etm_plan *p, void *dst, size_t bytes) {
+  if (!p || !dst) return fail(ETM_E_INVAL, "null argument");
+  if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  size_t need = 0;
+  etm_checkpoint_size(p, &need);
+  if (bytes < need) return fail(ETM_E_NOMEM, "checkpoint buffer too small");
+  CkptHeader h{kMagic, p->step, p->rec, p->n_thermal, p->cg_total, p->cur, p->th_cur, p->prec, p->n_solves, p->ntot};
+  char *o = static_cast<char *>(dst);
+  std::memcpy(o, &h, sizeof(h));
+  o += sizeof(h);
+  for (const Region *r : state_regions(p)) {
+    HIP_TRY(hipMemcpyAsync(o, p->ws + r->off, r->bytes, hipMemcpyDeviceToHost, p->stream));
+    o += r->bytes;
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return ETM_OK;
+}
+
+etm_status etm_restore(etm_plan *p, const void *src, size_t bytes) {
+  if (!p || !src) return fail(ETM_E_INVAL, "null argument");
+  if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  size_t need = 0;
+  etm_checkpoint_size(p, &need);
+  if (bytes < need) return fail(ETM_E_INVAL, "checkpoint too small");
+  CkptHeader h;
+  std::memcpy(&h, src, sizeof(h));
+  if (h.magic != kMagic || h.prec != p->prec || h.ntot != p->ntot) return fail(ETM_E_INVAL, "checkpoint does not match the plan");
+  const char *o = static_cast<const char *>(src) + sizeof(h);
+  for (const Region *r : state_regions(p)) {
+    HIP_TRY(hipMemcpyAsync(p->ws + r->off, o, r->bytes, hipMemcpyHostToDevice, p->stream));
+    o += r->bytes;
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->step = h.step; p->rec = h.rec; p->n_thermal = h.n_thermal; p->cg_total = h.cg_total;
+  p->cur = h.cur; p->th_cur = h.th_cur; p->n_solves = h.n_solves;
+  p->host_status = ETM_OK;
+  return ETM_OK;
+}
+
+void etm_plan_destroy(etm_plan *p) {
+  if (!p) return;
+  if (p->sc_host) (void)hipHostFree(p->sc_host);
+  delete p;
+}
+
+const char *etm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

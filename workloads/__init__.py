@@ -544,17 +544,24 @@ def random_problem(seed: int, nx: int, ny: int, nz: int, *, n_mat: int = 4, grad
         mat[nz - void_top:] = 0
     waves, plist = [], []
     T = n_steps * 1.5e-15
+    if em_bc is None:
+        em_bc = tuple(int(b) for b in rng.integers(0, 2, 6))
+
+    def pick(n, along, lo_pec, hi_pec):
+        if along:
+            return int(rng.integers(0, n))
+        cand = [v for v in range(n + 1) if not ((v == 0 and lo_pec) or (v == n and hi_pec))]
+        return int(cand[rng.integers(0, len(cand))])
+
     for p in range(n_ports):
         waves.append(Wave("gauss_cos", amp=amp * rng.uniform(0.5, 2.0), f0=rng.uniform(5e9, 50e9),
                           t0=T * rng.uniform(0.2, 0.6), tau=T * rng.uniform(0.1, 0.3)))
         d = int(rng.integers(0, 3))
-        i = int(rng.integers(0, nx if d == 0 else nx + 1))
-        j = int(rng.integers(0, ny if d == 1 else ny + 1))
-        k = int(rng.integers(0, nz if d == 2 else nz + 1))
+        i = pick(nx, d == 0, em_bc[0], em_bc[1])
+        j = pick(ny, d == 1, em_bc[2], em_bc[3])
+        k = pick(nz, d == 2, em_bc[4], em_bc[5])
         g = float(rng.uniform(0, 1e3)) if rng.random() < 0.5 else 0.0
         plist.append((d, i, j, k, p, float(rng.uniform(0.5, 1.5)), g))
-    if em_bc is None:
-        em_bc = tuple(int(b) for b in rng.integers(0, 2, 6))
     probes = np.array([[PROBE_EX, 0, 0, 0], [PROBE_THETA, nx // 2, ny // 2, nz // 2]], dtype=np.int64)
     return Problem(name=f"random{seed}_{nx}x{ny}x{nz}", dx=dx, dy=dy, dz=dz, mat=mat, props=props,
                    waves=waves, em_bc=tuple(em_bc), mech_bc=mech_bc, n_em_steps=n_steps,
