@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark: coupled Mcell-steps/s of the MI355X EM-thermal-mechanical path.
+
+Workload: the 256x256x64 graded package slice (4.19 M cells; substrate with
+16 PRBS-7-driven traces, 8x8 microbumps, TSV interposer, two dies), EM step
+at CFL 0.9, R = 200 EM steps per thermal step, a warm-started mechanical
+solve (rtol 1e-8) after every thermal step.
+
+One bench step = one coupling block: 200 EM steps (EM update + Joule
+source), one thermal step, one mechanical solve + von Mises, histories.
+`value` = cells * EM steps / wall time of the timed blocks, mechanics
+included; the march-only rate and CG DOF-iterations/s are reported beside
+it.  The headline runs the mixed path (FP32 fields, FP64 temperature /
+Joule / CG refinement); the same blocks are timed on the FP64 path.
+
+    python bench.py [--steps K] [--warmup W] [--precision mixed|fp64] [--no-fp64] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Compulsory bytes per cell-step of the fused EM step (one cell ~ one node +
+# three edges): FP64 e^n, e^{n-1} read + e^{n+1} written (72), material id
+# (1), temperature for sigma(T) (8), Joule accumulator read-modify-write (16);
+# mixed: e, delta read + written in FP32 (48), id (1), FP32 temperature (4),
+# Joule RMW (16).
+BYTES_PER_CELL_STEP = {"fp64": 97.0, "mixed": 69.0}
+# Compulsory bytes per DOF-iteration of Jacobi-PCG (vectors u, r, p, w and the
+# inverse diagonal streamed once per iteration): FP64 80, FP32 40.
+BYTES_PER_DOF_ITER = {"fp64": 80.0, "mixed": 40.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--probe", choices=["em", "em-fp64", "copy"], default=None,
+                    help="short runs for hardware-counter profiles: 20 EM steps of the workload, or a plain "
+                         "2 GiB device copy (the calibration kernel for FETCH_SIZE / WRITE_SIZE)")
+    return ap.parse_args()
+
+
+def probe(kind):
+    import torch
+    if kind == "copy":
+        x = torch.ones(1 << 28, dtype=torch.float64, device="cuda")  # 2 GiB
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy", "bytes_read_per_launch": x.numel() * 8,
+                          "bytes_written_per_launch": x.numel() * 8}))
+        return
+    import workloads as W
+    import paper_2603_07038_amd as etm
+    prob = W.config2()
+    prob.mech_every_thermal = 0
+    prob.em_per_thermal = 256  # 20 steps: no thermal step inside the probe
+    dt = etm.cfl_dt(prob)
+    J = prob.sample_J_half(dt, 64)
+    prec = etm.ETM_PREC_FP64 if kind == "em-fp64" else etm.ETM_PREC_MIXED
+    plan = etm.Plan(prob, J, dt=dt, precision=prec, n_steps=64, history=False)
+    plan.advance(20)
+    plan.sync()
+    print(json.dumps({"probe": kind, "workload": prob.name, "cells": prob.n_cells, "em_steps": 20}))
+
+
+PROFILE_EM = {"mixed": "profiles/em_march_slice256x256x64_mixed.md"}
+
+
+def measured_traffic(prec_name):
+    """HBM bytes per launch of the EM march from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel calibration);
+    None when no summary exists or the kernel source changed since it was taken."""
+    import hashlib
+    rel = PROFILE_EM.get(prec_name)
+    if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
+        return None
+    fields = {}
+    for line in open(os.path.join(ROOT, rel)):
+        if ":" in line and line.split(":")[0].strip() in ("traffic_bytes_per_launch", "traffic_source_sha256_16"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2603_07038_amd", "csrc", "em.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if fields.get("traffic_source_sha256_16") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
+def run_precision(prob, J, dt, prec_name, steps, warmup):
+    import torch
+    import paper_2603_07038_amd as etm
+    prec = etm.ETM_PREC_MIXED if prec_name == "mixed" else etm.ETM_PREC_FP64
+    R = prob.em_per_thermal
+    plan = etm.Plan(prob, J, dt=dt, precision=prec, n_steps=prob.n_em_steps)
+    stream = plan.stream
+    for _ in range(warmup):
+        plan.advance(R)
+    plan.sync()
+    info0 = plan.sync()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(steps):
+        ev[b][0].record(stream)
+        plan.advance(R - 1)            # EM steps only: the march kernel back to back
+        ev[b][1].record(stream)
+        plan.advance(1)                # last EM step + thermal + mechanical solve + von Mises
+        ev[b][2].record(stream)
+    info = plan.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    em_ms = sum(e[0].elapsed_time(e[1]) for e in ev)
+    tail_ms = sum(e[1].elapsed_time(e[2]) for e in ev)
+    cells = prob.n_cells
+    em_launch_s = em_ms / 1e3 / (steps * (R - 1))
+    iters = info["cg_iters_total"] - info0["cg_iters_total"]
+    _, _, mech_dofs = plan.dofs()
+    res = dict(
+        wall_s=wall,
+        ms_per_step=wall / steps * 1e3,
+        value=cells * R * steps / wall / 1e6,
+        march_mcell_steps_per_s=cells * (R - 1) * steps / (em_ms / 1e3) / 1e6,
+        em_kernel_us=em_launch_s * 1e6,
+        tail_ms_per_block=tail_ms / steps,
+        cg_iters=iters,
+        cg_dof_iter_per_s=(mech_dofs * iters / (tail_ms / 1e3)) if iters else None,
+        theta_max=info["theta_max"],
+        cg_relres=info["cg_relres"],
+        step_reached=info["step"],
+    )
+    bpc = BYTES_PER_CELL_STEP[prec_name]
+    achieved = bpc * cells / em_launch_s / 1e9
+    res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(prec_name),
+                       "traffic_unit": "bytes/launch", "algorithmic_bytes_per_launch": int(bpc * cells),
+                       "kernel": "em_march_kernel<%s>" % ("float,true" if prec_name == "mixed" else "double,false"),
+                       "launch_us": round(em_launch_s * 1e6, 2),
+                       "bytes_per_cell_step": bpc, "cells_per_launch": cells}
+    del plan
+    torch.cuda.synchronize()
+    return res
+
+
+def cpu_baseline(prob, dt, J, budget_s):
+    """The FP64 oracle as it stands, on the host cores: EM + Joule march steps
+    of the same workload (a bounded sample), in Mcell-steps/s."""
+    import oracle
+    o = oracle.Oracle(prob)
+    t = time.perf_counter()
+    st, _ = o.run(dt, 1, J, R=prob.em_per_thermal)
+    one = time.perf_counter() - t
+    n = max(1, min(int(budget_s / max(one, 1e-3)), 200))
+    t = time.perf_counter()
+    o.run(dt, n, J, state=st, R=prob.em_per_thermal)
+    el = time.perf_counter() - t
+    return {"value": round(prob.n_cells * n / el / 1e6, 3), "unit": "Mcell-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} EM+Joule steps of the {prob.nx}x{prob.ny}x{prob.nz} slice (FP64 oracle, mechanics "
+                      f"and thermal steps not in the sample), {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.probe:
+        probe(a.probe)
+        return
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_2603_07038_amd as etm
+    prob = W.config2()
+    dt = etm.cfl_dt(prob)
+    J = prob.sample_J_half(dt, prob.n_em_steps)
+    torch.cuda.init()
+    head = run_precision(prob, J, dt, a.precision, a.steps, a.warmup)
+    other = None
+    if not a.no_fp64 and a.precision == "mixed":
+        other = run_precision(prob, J, dt, "fp64", a.steps, a.warmup)
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(prob, dt, J, a.cpu_seconds)
+    out = {
+        "metric": "coupled Mcell-steps/s (EM + Joule + thermal march with a warm-started mechanical solve per "
+                  "thermal step)",
+        "value": round(head["value"], 2),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if a.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": prob.name, "cells": prob.n_cells, "grid": [prob.nx, prob.ny, prob.nz],
+                   "em_steps_per_step": prob.em_per_thermal, "dt_s": dt, "mech_solve_per_step": True,
+                   "cg_rtol": prob.cg_rtol, "precision": a.precision},
+        "march_mcell_steps_per_s": round(head["march_mcell_steps_per_s"], 1),
+        "em_kernel_us": round(head["em_kernel_us"], 2),
+        "mech_ms_per_step": round(head["tail_ms_per_block"], 2),
+        "cg_iters": head["cg_iters"],
+        "cg_dof_iter_per_s": head["cg_dof_iter_per_s"],
+        "roofline": head["roofline"],
+        "cpu_baseline": cpu,
+    }
+    if other:
+        out["fp64"] = {"value": round(other["value"], 2), "ms_per_step": round(other["ms_per_step"], 3),
+                       "march_mcell_steps_per_s": round(other["march_mcell_steps_per_s"], 1),
+                       "em_kernel_us": round(other["em_kernel_us"], 2), "cg_iters": other["cg_iters"],
+                       "cg_dof_iter_per_s": other["cg_dof_iter_per_s"], "roofline": other["roofline"]}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -85,6 +85,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_07038_amd.build`")
+    # torch ships its own HIP runtime; load it first so that libetm binds to the
+    # same runtime instance as the tensors and streams it is handed.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     sig = {
         "etm_opts_default": [C.POINTER(etm_opts)],
@@ -307,3 +310,38 @@ class Plan:
 
     def restore(self, buf):
         check(load().etm_restore(self.h, buf.ctypes.data, buf.nbytes))
+
+
+class Batch:
+    """Several bound plans advanced together (etm_batch_*): one launch per EM
+    step over all variants, chunks of steps replayed from HIP graphs."""
+
+    def __init__(self, max_slots, tune_json=None):
+        h = _P()
+        tj = None if tune_json is None else tune_json.encode()
+        check(load().etm_batch_create(int(max_slots), tj, C.byref(h)))
+        self.h = h
+        self.plans = {}
+
+    def attach(self, plan):
+        s = C.c_int32()
+        check(load().etm_batch_attach(self.h, plan.h, C.byref(s)))
+        self.plans[s.value] = plan
+        return s.value
+
+    def detach(self, slot):
+        check(load().etm_batch_detach(self.h, int(slot)))
+        self.plans.pop(slot, None)
+
+    def advance(self, n, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        check(load().etm_batch_advance(self.h, int(n), C.c_void_p(st.cuda_stream)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                load().etm_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass

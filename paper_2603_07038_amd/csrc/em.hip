@@ -10,129 +10,212 @@
 // (port conductances included), C the purely geometric curl-curl
 // (curl mu0^-1 curl = C / mu0) and jd = dt (J^{n+1/2} - J^{n-1/2}) / eps0.
 // The mixed path carries (e, delta = e^{n+1} - e^n) in FP32 and updates
-//   (er + a) delta^{n+1/2} = (er - a) delta^{n-1/2} - (c0 dt)^2 C e^n - jd,
+//   delta^{n+1/2} = delta^{n-1/2} - [2a delta^{n-1/2} + (c0 dt)^2 C e^n + jd] / (er + a),
 //   e^{n+1} = e^n + delta^{n+1/2},
 // which is the same recurrence rearranged so that FP32 rounding is not
-// integrated twice.
+// integrated twice and a lossless edge carries delta forward exactly.
+// Edge coefficients are always formed in FP64 and rounded once.
 //
-// One thread owns one node: it updates the x-, y- and z-edges that start at
-// the node and gathers the Joule power of all six edges that meet there.  The
-// three low-side edges belong to neighbouring threads, so their new values
-// are recomputed locally (the state is double/ping-pong buffered, so this
-// reads only old values) instead of being exchanged with atomics; the result
-// is deterministic.
+// March kernel.  A block owns a 64 x 4 column of nodes and marches up a
+// chunk of z planes, staging three e planes (k-1, k, k+1) with a one-node
+// halo in LDS, so each e value is fetched from memory once per step.  A node
+// updates the x-, y- and z-edges that start at it.  The Joule source is
+// gathered one step late: the node sums sigma e^2 L A over its six incident
+// edges of the *input* field e^n, which the stencil already holds, so no
+// edge update is recomputed and no atomics are needed.  The power of the
+// last step of a thermal block is added by the thermal kernel (or by a flush
+// kernel at the end of an advance call) before temperature changes.
+#include <algorithm>
+
 #include "etm_internal.h"
 
 namespace etm {
 
 namespace {
 
-constexpr int BX = 64, BY = 4;
+constexpr int BX = 64, BY = 4;             // threads per block (x, y)
+constexpr int TXH = BX + 2, TYH = BY + 2;  // staged tile with halo
 
+// ---- field accessors: value of component c at node offset (di, dj, dk) --
 template <typename T>
-struct Ld1 {
-  const T *a;
-  __device__ __forceinline__ T operator[](int64_t i) const { return a[i]; }
+struct GAcc {  // global memory around node n
+  const T *e[3];
+  int64_t n, sy, sz;
+  __device__ __forceinline__ T raw(int c, int di, int dj, int dk) const { return e[c][n + di + dj * sy + dk * sz]; }
+  __device__ __forceinline__ double operator()(int c, int di, int dj, int dk) const { return double(raw(c, di, dj, dk)); }
 };
 template <typename T>
-struct LdDiff {  // a - b (e^n recovered from e^{n+1} and delta in the mixed diagnostics)
-  const T *a, *b;
-  __device__ __forceinline__ T operator[](int64_t i) const { return a[i] - b[i]; }
+struct GDiff {  // a - b (e^n recovered from e^{n+1} and delta)
+  const T *a[3], *b[3];
+  int64_t n, sy, sz;
+  __device__ __forceinline__ T raw(int c, int di, int dj, int dk) const {
+    const int64_t q = n + di + dj * sy + dk * sz;
+    return a[c][q] - b[c][q];
+  }
+  __device__ __forceinline__ double operator()(int c, int di, int dj, int dk) const { return double(raw(c, di, dj, dk)); }
+};
+template <typename T>
+struct SAcc {  // LDS ring: slot[dk+1] holds plane k+dk
+  const T (*sh)[3][TYH][TXH];
+  int slot[3];
+  int li, lj;
+  __device__ __forceinline__ T raw(int c, int di, int dj, int dk) const { return sh[slot[dk + 1]][c][lj + dj][li + di]; }
+  __device__ __forceinline__ double operator()(int c, int di, int dj, int dk) const { return double(raw(c, di, dj, dk)); }
 };
 
 // ---- geometric curl-curl (C e) at the edge of direction D starting at node
-// (i,j,k) = index n.  h on a primal face = circulation / area (mu0 dropped);
-// faces outside the domain carry zero (PMC truncation).
-template <typename T, typename LD>
-__device__ __forceinline__ T curl_x(const DevGrid &g, const LD &ex, const LD &ey, const LD &ez, int i, int j,
-                                    int k, int64_t n) {
+// (i,j,k).  h on a primal face = circulation / area (mu0 dropped); faces
+// outside the domain carry zero (PMC truncation).
+template <typename T, typename A>
+__device__ __forceinline__ T curl_x(const DevGrid &g, const A &E, int i, int j, int k) {
   const T idxi = T(g.idx[i]);
   T s = T(0);
-  if (j < g.ny) s += ((ex[n] - ex[n + g.sy]) * T(g.idy[j]) + (ey[n + 1] - ey[n]) * idxi) * T(g.ihy[j]);
-  if (j > 0)
-    s -= ((ex[n - g.sy] - ex[n]) * T(g.idy[j - 1]) + (ey[n - g.sy + 1] - ey[n - g.sy]) * idxi) * T(g.ihy[j]);
-  if (k < g.nz) s -= ((ez[n] - ez[n + 1]) * idxi + (ex[n + g.sz] - ex[n]) * T(g.idz[k])) * T(g.ihz[k]);
-  if (k > 0)
-    s += ((ez[n - g.sz] - ez[n - g.sz + 1]) * idxi + (ex[n] - ex[n - g.sz]) * T(g.idz[k - 1])) * T(g.ihz[k]);
+  if (j < g.ny) s += ((E.raw(0, 0, 0, 0) - E.raw(0, 0, 1, 0)) * T(g.idy[j]) + (E.raw(1, 1, 0, 0) - E.raw(1, 0, 0, 0)) * idxi) * T(g.ihy[j]);
+  if (j > 0) s -= ((E.raw(0, 0, -1, 0) - E.raw(0, 0, 0, 0)) * T(g.idy[j - 1]) + (E.raw(1, 1, -1, 0) - E.raw(1, 0, -1, 0)) * idxi) * T(g.ihy[j]);
+  if (k < g.nz) s -= ((E.raw(2, 0, 0, 0) - E.raw(2, 1, 0, 0)) * idxi + (E.raw(0, 0, 0, 1) - E.raw(0, 0, 0, 0)) * T(g.idz[k])) * T(g.ihz[k]);
+  if (k > 0) s += ((E.raw(2, 0, 0, -1) - E.raw(2, 1, 0, -1)) * idxi + (E.raw(0, 0, 0, 0) - E.raw(0, 0, 0, -1)) * T(g.idz[k - 1])) * T(g.ihz[k]);
   return s;
 }
-
-template <typename T, typename LD>
-__device__ __forceinline__ T curl_y(const DevGrid &g, const LD &ex, const LD &ey, const LD &ez, int i, int j,
-                                    int k, int64_t n) {
+template <typename T, typename A>
+__device__ __forceinline__ T curl_y(const DevGrid &g, const A &E, int i, int j, int k) {
   const T idyj = T(g.idy[j]);
   T s = T(0);
-  // + [hx(k) - hx(k-1)] / hz
-  if (k < g.nz) s += ((ez[n + g.sy] - ez[n]) * idyj - (ey[n + g.sz] - ey[n]) * T(g.idz[k])) * T(g.ihz[k]);
-  if (k > 0)
-    s -= ((ez[n - g.sz + g.sy] - ez[n - g.sz]) * idyj - (ey[n] - ey[n - g.sz]) * T(g.idz[k - 1])) * T(g.ihz[k]);
-  // - [hz(i) - hz(i-1)] / hx
-  if (i < g.nx) s -= ((ex[n] - ex[n + g.sy]) * idyj + (ey[n + 1] - ey[n]) * T(g.idx[i])) * T(g.ihx[i]);
-  if (i > 0)
-    s += ((ex[n - 1] - ex[n - 1 + g.sy]) * idyj + (ey[n] - ey[n - 1]) * T(g.idx[i - 1])) * T(g.ihx[i]);
+  if (k < g.nz) s += ((E.raw(2, 0, 1, 0) - E.raw(2, 0, 0, 0)) * idyj - (E.raw(1, 0, 0, 1) - E.raw(1, 0, 0, 0)) * T(g.idz[k])) * T(g.ihz[k]);
+  if (k > 0) s -= ((E.raw(2, 0, 1, -1) - E.raw(2, 0, 0, -1)) * idyj - (E.raw(1, 0, 0, 0) - E.raw(1, 0, 0, -1)) * T(g.idz[k - 1])) * T(g.ihz[k]);
+  if (i < g.nx) s -= ((E.raw(0, 0, 0, 0) - E.raw(0, 0, 1, 0)) * idyj + (E.raw(1, 1, 0, 0) - E.raw(1, 0, 0, 0)) * T(g.idx[i])) * T(g.ihx[i]);
+  if (i > 0) s += ((E.raw(0, -1, 0, 0) - E.raw(0, -1, 1, 0)) * idyj + (E.raw(1, 0, 0, 0) - E.raw(1, -1, 0, 0)) * T(g.idx[i - 1])) * T(g.ihx[i]);
   return s;
 }
-
-template <typename T, typename LD>
-__device__ __forceinline__ T curl_z(const DevGrid &g, const LD &ex, const LD &ey, const LD &ez, int i, int j,
-                                    int k, int64_t n) {
+template <typename T, typename A>
+__device__ __forceinline__ T curl_z(const DevGrid &g, const A &E, int i, int j, int k) {
   const T idzk = T(g.idz[k]);
   T s = T(0);
-  // + [hy(i) - hy(i-1)] / hx
-  if (i < g.nx) s += ((ez[n] - ez[n + 1]) * T(g.idx[i]) + (ex[n + g.sz] - ex[n]) * idzk) * T(g.ihx[i]);
-  if (i > 0)
-    s -= ((ez[n - 1] - ez[n]) * T(g.idx[i - 1]) + (ex[n - 1 + g.sz] - ex[n - 1]) * idzk) * T(g.ihx[i]);
-  // - [hx(j) - hx(j-1)] / hy
-  if (j < g.ny) s -= ((ez[n + g.sy] - ez[n]) * T(g.idy[j]) - (ey[n + g.sz] - ey[n]) * idzk) * T(g.ihy[j]);
-  if (j > 0)
-    s += ((ez[n] - ez[n - g.sy]) * T(g.idy[j - 1]) - (ey[n - g.sy + g.sz] - ey[n - g.sy]) * idzk) * T(g.ihy[j]);
+  if (i < g.nx) s += ((E.raw(2, 0, 0, 0) - E.raw(2, 1, 0, 0)) * T(g.idx[i]) + (E.raw(0, 0, 0, 1) - E.raw(0, 0, 0, 0)) * idzk) * T(g.ihx[i]);
+  if (i > 0) s -= ((E.raw(2, -1, 0, 0) - E.raw(2, 0, 0, 0)) * T(g.idx[i - 1]) + (E.raw(0, -1, 0, 1) - E.raw(0, -1, 0, 0)) * idzk) * T(g.ihx[i]);
+  if (j < g.ny) s -= ((E.raw(2, 0, 1, 0) - E.raw(2, 0, 0, 0)) * T(g.idy[j]) - (E.raw(1, 0, 0, 1) - E.raw(1, 0, 0, 0)) * idzk) * T(g.ihy[j]);
+  if (j > 0) s += ((E.raw(2, 0, 0, 0) - E.raw(2, 0, -1, 0)) * T(g.idy[j - 1]) - (E.raw(1, 0, -1, 1) - E.raw(1, 0, -1, 0)) * idzk) * T(g.ihy[j]);
   return s;
 }
 
-template <typename T, int D, typename LD>
-__device__ __forceinline__ T curl_d(const DevGrid &g, const LD &ex, const LD &ey, const LD &ez, int i, int j,
-                                    int k, int64_t n) {
-  if (D == 0) return curl_x<T>(g, ex, ey, ez, i, j, k, n);
-  if (D == 1) return curl_y<T>(g, ex, ey, ez, i, j, k, n);
-  return curl_z<T>(g, ex, ey, ez, i, j, k, n);
+__device__ __forceinline__ bool pec_edge(const DevGrid &g, int D, int i, int j, int k) {
+  const int b = g.pec;
+  if (D != 0 && ((i == 0 && (b & 1)) || (i == g.nx && (b & 2)))) return true;
+  if (D != 1 && ((j == 0 && (b & 4)) || (j == g.ny && (b & 8)))) return true;
+  if (D != 2 && ((k == 0 && (b & 16)) || (k == g.nz && (b & 32)))) return true;
+  return false;
 }
 
-// ---- edge materials: sums over the up-to-four cells around the edge of
-// (quarter of the transverse dual area in the cell) * property.  Divided by
-// the dual area they give the area-weighted means; sigma per cell follows
-// Eq. (6) at the edge-midpoint rise.
-template <typename T, int D>
-__device__ __forceinline__ void edge_sums(const DevGrid &g, int i, int j, int k, int64_t n, T th, T &epsA,
-                                          T &sigA) {
-  epsA = T(0);
-  sigA = T(0);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    int a0 = (c & 1) - 1, b0 = (c >> 1) - 1;  // offsets -1/0 in the two transverse directions
-    int ii = i, jj = j, kk = k;
-    T w;
-    if (D == 0) {
-      jj = j + a0; kk = k + b0;
-      if (jj < 0 || jj >= g.ny || kk < 0 || kk >= g.nz) continue;
-      w = T(0.25) * T(g.dy[jj]) * T(g.dz[kk]);
-    } else if (D == 1) {
-      ii = i + a0; kk = k + b0;
-      if (ii < 0 || ii >= g.nx || kk < 0 || kk >= g.nz) continue;
-      w = T(0.25) * T(g.dx[ii]) * T(g.dz[kk]);
-    } else {
-      ii = i + a0; jj = j + b0;
-      if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny) continue;
-      w = T(0.25) * T(g.dx[ii]) * T(g.dy[jj]);
-    }
-    const int m = g.mat[n + (ii - i) + (jj - j) * g.sy + (kk - k) * g.sz];
-    const double *row = g.mtab + m * kMatStride;
-    epsA += w * T(row[MC_EPSR]);
-    T s = T(row[MC_SIGS]);
-    const T t = T(row[MC_TCR]);
-    if (t != T(0)) s = s / (T(1) + t * th);
-    sigA += w * s;
+// ---- 1D tables, from one base pointer (dx, dy, dz, idx, idy, idz, hx, hy, hz,
+// ihx, ihy, ihz, then alpha_lo / alpha_hi per axis on nodes).
+struct Geo {
+  const double *dx, *dy, *dz, *idx, *idy, *idz, *ihx, *ihy, *ihz, *axl, *axh, *ayl, *ayh, *azl, *azh;
+  __device__ __forceinline__ Geo(const double *g, int nx, int ny, int nz) {
+    dx = g; dy = dx + nx; dz = dy + ny;
+    idx = dz + nz; idy = idx + nx; idz = idy + ny;
+    const double *hx = idz + nz, *hy = hx + nx + 1, *hz = hy + ny + 1;
+    ihx = hz + nz + 1; ihy = ihx + nx + 1; ihz = ihy + ny + 1;
+    axl = ihz + nz + 1; axh = axl + nx + 1; ayl = axh + nx + 1; ayh = ayl + ny + 1;
+    azl = ayh + ny + 1; azh = azl + nz + 1;
   }
+};
+
+// ---- edge coefficients from the cells around a node -----------------------
+// Cell (i-1+ox, j-1+oy, k-1+oz) touches the node's x-edge on side ox (the
+// edge starting at the node if ox = 1, the low-side edge i-1 if ox = 0), its
+// y-edge on side oy and its z-edge on side oz.  An edge property is the mean
+// over its cells weighted by the share of the edge's dual area in each cell;
+// on a rectilinear grid that share factors into alpha_y(oy) * alpha_z(oz)
+// for an x-edge (alpha = half the cell width over the node's dual width, 0 for
+// a cell outside the mesh).  sigma follows Eq. (6) per cell at the
+// edge-midpoint rise.  Returned: the normalised conductance
+// a = dt sigma / (2 eps0) and (own edges) the mean eps_r.  FP64 with explicit
+// FMAs and contraction off, so every kernel that calls it gets the same bits.
+struct CellV {
+  double er, sg;  // eps_r, sigma0 * dt / (2 eps0)
+  int tf, m;      // sigma depends on temperature; material id
+};
+
+template <int D, typename CELL, typename TCR, typename TH>
+__device__ __forceinline__ double edge_coef(int side, const double (&ax)[2], const double (&ay)[2],
+                                            const double (&az)[2], const CELL &cell, const TCR &tcr_of, const TH &th,
+                                            double *er_out) {
+#pragma clang fp contract(off)
+  double er = 0.0, sg = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int p0 = q & 1, p1 = q >> 1;  // offsets in the two transverse directions
+    const int ox = D == 0 ? side : p0, oy = D == 1 ? side : (D == 0 ? p0 : p1), oz = D == 2 ? side : p1;
+    const double w = D == 0 ? ay[oy] * az[oz] : D == 1 ? ax[ox] * az[oz] : ax[ox] * ay[oy];
+    const CellV v = cell(ox, oy, oz);
+    double s0 = v.sg;
+    if (v.tf && w != 0.0) {
+      const double t0 = th(0, 0, 0);
+      const double t1 = D == 0 ? th(side ? 1 : -1, 0, 0) : D == 1 ? th(0, side ? 1 : -1, 0) : th(0, 0, side ? 1 : -1);
+      s0 = s0 / (1.0 + tcr_of(v.m) * (0.5 * (t0 + t1)));
+    }
+    sg = fma(w, s0, sg);
+    if (er_out) er = fma(w, v.er, er);
+  }
+  if (er_out) *er_out = er;
+  return sg;
 }
+
+// Joule power density at the node from its six incident edges of field e:
+//   P_n = sum_e 1/2 sigma_e e^2 L A / V_n = jf * sum_e a_e e^2 (L / dual width),
+// with L / dual width = 2 alpha on the edge's side (0 for a missing edge).
+// a[0..5], v[0..5]: own x, y, z then low-side x, y, z.
+__device__ __forceinline__ double node_joule(const double (&a)[6], const double (&ax)[2], const double (&ay)[2],
+                                             const double (&az)[2], const double (&v)[6], double jf) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+  s = fma(ax[1] * a[0], v[0] * v[0], s);
+  s = fma(ay[1] * a[1], v[1] * v[1], s);
+  s = fma(az[1] * a[2], v[2] * v[2], s);
+  s = fma(ax[0] * a[3], v[3] * v[3], s);
+  s = fma(ay[0] * a[4], v[4] * v[4], s);
+  s = fma(az[0] * a[5], v[5] * v[5], s);
+  return (2.0 * jf) * s;
+}
+
+// Conductances of the three low-side edges (for the Joule source).
+template <typename CELL, typename TCR, typename TH>
+__device__ __forceinline__ void low_coefs(const double (&ax)[2], const double (&ay)[2], const double (&az)[2],
+                                          const CELL &cell, const TCR &tcr_of, const TH &th, double (&a)[6]) {
+  a[3] = edge_coef<0>(0, ax, ay, az, cell, tcr_of, th, nullptr);
+  a[4] = edge_coef<1>(0, ax, ay, az, cell, tcr_of, th, nullptr);
+  a[5] = edge_coef<2>(0, ax, ay, az, cell, tcr_of, th, nullptr);
+}
+
+// The 8 cells around node (i,j,k) from global memory (cells outside the
+// mesh read as material 0; their weights are 0).
+struct GCell {
+  const uint8_t *m;
+  const double *mtab;
+  int64_t n, sy, sz;
+  int i, j, k, nx, ny, nz;
+  __device__ __forceinline__ CellV operator()(int ox, int oy, int oz) const {
+    const int ci = i - 1 + ox, cj = j - 1 + oy, ck = k - 1 + oz;
+    const bool ok = !(ci < 0 || ci >= nx || cj < 0 || cj >= ny || ck < 0 || ck >= nz);
+    const int mm = ok ? int(m[n + (ox - 1) + (oy - 1) * sy + (oz - 1) * sz]) : 0;
+    const double *row = mtab + mm * kMatStride;
+    CellV v;
+    v.er = row[MC_EPSR];
+    v.sg = row[MC_SIGS];
+    v.tf = (row[MC_TCR] != 0.0 && v.sg != 0.0) ? 1 : 0;
+    v.m = mm;
+    return v;
+  }
+};
+struct GTcr {
+  const double *mtab;
+  __device__ __forceinline__ double operator()(int m) const { return mtab[m * kMatStride + MC_TCR]; }
+};
+template <typename T>
+struct GTh {
+  const T *th;
+  int64_t n, sy, sz;
+  __device__ __forceinline__ double operator()(int di, int dj, int dk) const { return double(th[n + di + dj * sy + dk * sz]); }
+};
 
 __device__ __forceinline__ int find_port(const DevPorts &P, int64_t key) {
   int lo = 0, hi = P.n_edges - 1;
@@ -145,107 +228,240 @@ __device__ __forceinline__ int find_port(const DevPorts &P, int64_t key) {
   return -1;
 }
 
-template <typename T>
-struct EmPtrs {
-  const T *e[3];    // e^n
-  const T *aux[3];  // FP64: e^{n-1};  mixed: delta^{n-1/2}
-  T *oe[3];         // e^{n+1}
-  T *oaux[3];       // mixed: delta^{n+1/2}
+// Source and lumped conductance of the port edge (key) at this step.
+struct PortTerm {
+  double jd, g;
 };
-
-__device__ __forceinline__ bool pec_edge(const DevGrid &g, int D, int i, int j, int k) {
-  const int b = g.pec;
-  if (D != 0 && ((i == 0 && (b & 1)) || (i == g.nx && (b & 2)))) return true;
-  if (D != 1 && ((j == 0 && (b & 4)) || (j == g.ny && (b & 8)))) return true;
-  if (D != 2 && ((k == 0 && (b & 16)) || (k == g.nz && (b & 32)))) return true;
-  return false;
+__device__ __forceinline__ PortTerm port_terms(const DevPorts &P, int64_t key, int64_t step) {
+  PortTerm r{0.0, 0.0};
+  const int q = find_port(P, key);
+  if (q < 0) return r;
+  r.g = P.gs[q];
+  const int64_t s1 = step + 1, s0 = step, ns = P.n_samples;
+  for (int t = P.start[q]; t < P.start[q + 1]; ++t) {
+    const double *Jw = P.J + int64_t(P.wave[t]) * ns;
+    const double j1 = s1 < ns ? Jw[s1] : 0.0, j0 = s0 < ns ? Jw[s0] : 0.0;
+    r.jd += P.wt[t] * (j1 - j0);
+  }
+  return r;
 }
 
-// New value of one edge; sigA (material conductance sum, for the Joule
-// source) and the increment are returned by reference.
-template <typename T, int D, bool INC>
-__device__ __forceinline__ T edge_new(const EmLaunch &L, const EmPtrs<T> &p, const T *th, int i, int j, int k,
-                                      int64_t n, T &sigA, T &delta) {
+// 1/x in FP64: hardware reciprocal and two Newton steps (full precision).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// LDS staging of one block: three e planes (k-1, k, k+1) of the 64 x 4 node
+// column with a one-node halo.
+template <typename T>
+struct MarchSmem {
+  T e[3][3][TYH][TXH];
+};
+
+template <typename T>
+struct EmPtrs {
+  const T *e;    // e^n (component c at + c*cs)
+  const T *aux;  // FP64: e^{n-1};  mixed: delta^{n-1/2}
+  T *oe;         // e^{n+1}
+  T *oaux;       // mixed: delta^{n+1/2}
+};
+
+// Joule power density at node n from the stored coefficients of its six
+// incident edges and their field values v (own x, y, z, low x, y, z).  The
+// same code serves the march kernel and the flush / thermal kernels.
+// The mixed path stores 2a, so its conductances are halved (exactly) here.
+template <typename T>
+__device__ __forceinline__ double joule_from_coef(const T *cf, uint32_t cs, uint32_t n, uint32_t sy, uint32_t sz,
+                                                  int i, int j, int k, const double (&ax)[2], const double (&ay)[2],
+                                                  const double (&az)[2], const double (&v)[6], double jf) {
+  const double h = sizeof(T) == 4 ? 0.5 : 1.0;
+  const double a6[6] = {h * double(cf[3 * cs + n]), h * double(cf[4 * cs + n]), h * double(cf[5 * cs + n]),
+                        i > 0 ? h * double(cf[3 * cs + n - 1]) : 0.0, j > 0 ? h * double(cf[4 * cs + n - sy]) : 0.0,
+                        k > 0 ? h * double(cf[5 * cs + n - sz]) : 0.0};
+  return node_joule(a6, ax, ay, az, v, jf);
+}
+
+// One block: the 64 x 4 node column (tx, ty) over the z planes of chunk kc.
+// Per plane: stage e plane k+1, update the own edges of the nodes of plane
+// k from their stored coefficients, and gather the Joule power of e^n at the
+// node from its six incident edges.
+template <typename T, bool INC>
+__device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T> &p, int64_t step, int tx, int ty,
+                                              int kc, int kchunk, int acc_joule, MarchSmem<T> &S) {
   const DevGrid &g = L.g;
-  if (pec_edge(g, D, i, j, k)) { sigA = T(0); delta = T(0); return T(0); }
-  const int64_t nb = n + (D == 0 ? 1 : D == 1 ? g.sy : g.sz);
-  const T th_e = T(0.5) * (th[n] + th[nb]);
-  T epsA;
-  edge_sums<T, D>(g, i, j, k, n, th_e, epsA, sigA);
-  const T iA = D == 0 ? T(g.ihy[j] * g.ihz[k]) : D == 1 ? T(g.ihx[i] * g.ihz[k]) : T(g.ihx[i] * g.ihy[j]);
-  const T er = epsA * iA;
-  T a = sigA * iA;
-  T jd = T(0);
-  if (g.flags[n] & (1 << D)) {
-    const int q = find_port(L.ports, int64_t(D) * g.ntot + n);
-    if (q >= 0) {
-      a += T(L.ports.gs[q]);
-      double acc = 0.0;
-      const int64_t s1 = L.step + 1, s0 = L.step, ns = L.ports.n_samples;
-      for (int t = L.ports.start[q]; t < L.ports.start[q + 1]; ++t) {
-        const double *Jw = L.ports.J + int64_t(L.ports.wave[t]) * ns;
-        const double j1 = s1 < ns ? Jw[s1] : 0.0, j0 = s0 < ns ? Jw[s0] : 0.0;
-        acc += L.ports.wt[t] * (j1 - j0);
-      }
-      jd = T(acc);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const uint32_t sy = uint32_t(g.sy), sz = uint32_t(g.sz), cs = g.cs;
+  const Geo G(g.geo, nx, ny, nz);
+  const T *cf = static_cast<const T *>(L.coef);
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * BX + lx;
+  const int i0 = tx * BX, j0 = ty * BY;
+  const int i = i0 + lx, j = j0 + ly;
+  const int k0 = kc * kchunk, k1 = min(k0 + kchunk, nz + 1);
+  auto load_plane = [&](int kk, int slot) {
+    for (int t = tid; t < TYH * TXH; t += BX * BY) {
+      const int r = t / TXH, c = t - r * TXH;
+      const int gi = i0 - 1 + c, gj = j0 - 1 + r;
+      const bool ok = kk >= 0 && kk <= nz && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny;
+      const uint32_t q = uint32_t(kk) * sz + uint32_t(gj) * sy + uint32_t(gi);
+      S.e[slot][0][r][c] = ok ? p.e[q] : T(0);
+      S.e[slot][1][r][c] = ok ? p.e[cs + q] : T(0);
+      S.e[slot][2][r][c] = ok ? p.e[2 * cs + q] : T(0);
     }
+  };
+  // per-thread x / y factors (clamped indices; masks select the valid terms)
+  const bool active = i <= nx && j <= ny;
+  const int ic = min(i, nx), jc = min(j, ny);
+  const double ax[2] = {G.axl[ic], G.axh[ic]}, ay[2] = {G.ayl[jc], G.ayh[jc]};
+  const T idx_i = T(G.idx[min(ic, nx - 1)]), idx_m = T(G.idx[max(ic - 1, 0)]), ihx_i = T(G.ihx[ic]);
+  const T idy_j = T(G.idy[min(jc, ny - 1)]), idy_m = T(G.idy[max(jc - 1, 0)]), ihy_j = T(G.ihy[jc]);
+  const T vi0 = T(i > 0), vi1 = T(i < nx), vj0 = T(j > 0), vj1 = T(j < ny);
+  const T c2 = T(L.c2dt2);
+  const int pec = g.pec;
+  const bool pec_i = (i == 0 && (pec & 1)) || (i == nx && (pec & 2));
+  const bool pec_j = (j == 0 && (pec & 4)) || (j == ny && (pec & 8));
+  int s_m = 0, s_0 = 1, s_p = 2;
+  load_plane(k0 - 1, s_m);
+  load_plane(k0, s_0);
+  for (int k = k0; k < k1; ++k) {
+    load_plane(k + 1, s_p);
+    __syncthreads();
+    if (active) {
+      const uint32_t n = uint32_t(k) * sz + uint32_t(j) * sy + uint32_t(i);
+      const T idz_k = T(G.idz[min(k, nz - 1)]), idz_m = T(G.idz[max(k - 1, 0)]), ihz_k = T(G.ihz[k]);
+      const T vk0 = T(k > 0), vk1 = T(k < nz);
+      const bool pec_k = (k == 0 && (pec & 16)) || (k == nz && (pec & 32));
+      auto E = [&](int c, int di, int dj, int dk) -> T {
+        const int sl = dk < 0 ? s_m : dk > 0 ? s_p : s_0;
+        return S.e[sl][c][ly + 1 + dj][lx + 1 + di];
+      };
+      const uint8_t fl = (g.flags[n] & 7);
+      // curl-curl of e^n on the three own edges (faces outside the mesh masked to 0)
+      const T e0x = E(0, 0, 0, 0), e0y = E(1, 0, 0, 0), e0z = E(2, 0, 0, 0);
+      const T hz_c = (e0x - E(0, 0, 1, 0)) * idy_j + (E(1, 1, 0, 0) - e0y) * idx_i;        // hz(i, j)
+      const T hy_c = (e0z - E(2, 1, 0, 0)) * idx_i + (E(0, 0, 0, 1) - e0x) * idz_k;        // hy(i, k)
+      const T hx_c = (E(2, 0, 1, 0) - e0z) * idy_j - (E(1, 0, 0, 1) - e0y) * idz_k;        // hx(j, k)
+      const bool pec_d[3] = {pec_j || pec_k, pec_i || pec_k, pec_i || pec_j};
+#pragma unroll
+      for (int D = 0; D < 3; ++D) {
+        const bool exists = D == 0 ? i < nx : D == 1 ? j < ny : k < nz;
+        if (!exists) continue;
+        const uint32_t o = D * cs + n;
+        if (pec_d[D]) {
+          p.oe[o] = T(0);
+          if (INC) p.oaux[o] = T(0);
+          continue;
+        }
+        T cc;
+        if (D == 0) {
+          const T hz_jm = (E(0, 0, -1, 0) - e0x) * idy_m + (E(1, 1, -1, 0) - E(1, 0, -1, 0)) * idx_i;
+          const T hy_km = (E(2, 0, 0, -1) - E(2, 1, 0, -1)) * idx_i + (e0x - E(0, 0, 0, -1)) * idz_m;
+          cc = (vj1 * hz_c - vj0 * hz_jm) * ihy_j - (vk1 * hy_c - vk0 * hy_km) * ihz_k;
+        } else if (D == 1) {
+          const T hx_km = (E(2, 0, 1, -1) - E(2, 0, 0, -1)) * idy_j - (e0y - E(1, 0, 0, -1)) * idz_m;
+          const T hz_im = (E(0, -1, 0, 0) - E(0, -1, 1, 0)) * idy_j + (e0y - E(1, -1, 0, 0)) * idx_m;
+          cc = (vk1 * hx_c - vk0 * hx_km) * ihz_k - (vi1 * hz_c - vi0 * hz_im) * ihx_i;
+        } else {
+          const T hy_im = (E(2, -1, 0, 0) - e0z) * idx_m + (E(0, -1, 0, 1) - E(0, -1, 0, 0)) * idz_k;
+          const T hx_jm = (e0z - E(2, 0, -1, 0)) * idy_m - (E(1, 0, -1, 1) - E(1, 0, -1, 0)) * idz_k;
+          cc = (vi1 * hy_c - vi0 * hy_im) * ihx_i - (vj1 * hx_c - vj0 * hx_jm) * ihy_j;
+        }
+        const T e0 = D == 0 ? e0x : D == 1 ? e0y : e0z;
+        if (INC) {
+          // stored: 1/(er + a) and 2a, each rounded once from FP64
+          T inv = cf[D * cs + n], a2 = cf[(3 + D) * cs + n], jd = T(0);
+          if (fl & (1 << D)) {
+            const int q = find_port(L.ports, int64_t(D) * g.ntot + n);
+            const PortTerm pt = port_terms(L.ports, int64_t(D) * g.ntot + n, step);
+            const double a = 0.5 * double(a2) + pt.g;
+            inv = T(rcp64(L.ports.er[q] + a));
+            a2 = T(2.0 * a);
+            jd = T(pt.jd);
+          }
+          const T d0 = p.aux[o];
+          const T d1 = d0 - (a2 * d0 + c2 * cc + jd) * inv;
+          p.oaux[o] = d1;
+          p.oe[o] = e0 + d1;
+        } else {
+          T er = cf[D * cs + n], a = cf[(3 + D) * cs + n], jd = T(0);
+          if (fl & (1 << D)) {
+            const PortTerm pt = port_terms(L.ports, int64_t(D) * g.ntot + n, step);
+            a = T(double(a) + pt.g);
+            jd = T(pt.jd);
+          }
+          const T inv = T(rcp64(double(er) + double(a)));
+          p.oe[o] = (T(2) * er * e0 - c2 * cc - (er - a) * p.aux[o] - jd) * inv;
+        }
+      }
+      if (acc_joule) {
+        const double az[2] = {G.azl[k], G.azh[k]};
+        const double v[6] = {double(e0x), double(e0y), double(e0z), double(E(0, -1, 0, 0)), double(E(1, 0, -1, 0)),
+                             double(E(2, 0, 0, -1))};
+        const double P = joule_from_coef(cf, cs, n, sy, sz, i, j, k, ax, ay, az, v, L.jf);
+        if (P != 0.0) L.psum[n] += P;
+      }
+    }
+    __syncthreads();
+    const int t = s_m;
+    s_m = s_0; s_0 = s_p; s_p = t;
   }
-  Ld1<T> ex{p.e[0]}, ey{p.e[1]}, ez{p.e[2]};
-  const T cc = curl_d<T, D>(g, ex, ey, ez, i, j, k, n);
-  const T e0 = p.e[D][n];
-  const T inv = T(1) / (er + a);
-  if (INC) {
-    delta = ((er - a) * p.aux[D][n] - T(L.c2dt2) * cc - jd) * inv;
-    return e0 + delta;
-  } else {
-    const T en = (T(2) * er * e0 - T(L.c2dt2) * cc - (er - a) * p.aux[D][n] - jd) * inv;
-    delta = en - e0;
-    return en;
-  }
+}
+
+// Block b of nb is dispatched to XCD b % 8; give each XCD a contiguous
+// range of logical tiles so neighbouring columns share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb / 8, r = nb % 8, x = b % 8, pos = b / 8;
+  return x * q + min(x, r) + pos;
 }
 
 template <typename T, bool INC>
-__global__ __launch_bounds__(256) void em_step_kernel(EmLaunch L, EmPtrs<T> p, const T *th) {
-  const DevGrid &g = L.g;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  if (i > g.nx || j > g.ny) return;
-  const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
-  T jsum = T(0), s, d;
-  if (i < g.nx) {
-    const T e1 = edge_new<T, 0, INC>(L, p, th, i, j, k, n, s, d);
-    p.oe[0][n] = e1;
-    if (INC) p.oaux[0][n] = d;
-    jsum += e1 * e1 * T(g.dx[i]) * s;
-  }
-  if (j < g.ny) {
-    const T e1 = edge_new<T, 1, INC>(L, p, th, i, j, k, n, s, d);
-    p.oe[1][n] = e1;
-    if (INC) p.oaux[1][n] = d;
-    jsum += e1 * e1 * T(g.dy[j]) * s;
-  }
-  if (k < g.nz) {
-    const T e1 = edge_new<T, 2, INC>(L, p, th, i, j, k, n, s, d);
-    p.oe[2][n] = e1;
-    if (INC) p.oaux[2][n] = d;
-    jsum += e1 * e1 * T(g.dz[k]) * s;
-  }
-  if (i > 0) {
-    const T e1 = edge_new<T, 0, INC>(L, p, th, i - 1, j, k, n - 1, s, d);
-    jsum += e1 * e1 * T(g.dx[i - 1]) * s;
-  }
-  if (j > 0) {
-    const T e1 = edge_new<T, 1, INC>(L, p, th, i, j - 1, k, n - g.sy, s, d);
-    jsum += e1 * e1 * T(g.dy[j - 1]) * s;
-  }
-  if (k > 0) {
-    const T e1 = edge_new<T, 2, INC>(L, p, th, i, j, k - 1, n - g.sz, s, d);
-    jsum += e1 * e1 * T(g.dz[k - 1]) * s;
-  }
-  // P_n = sum_e 1/2 sigma_e e^2 L A / V_n  =  jf * sum_e e^2 L sigA / V_n
-  L.psum[n] += double(jsum) * L.jf * (g.ihx[i] * g.ihy[j] * g.ihz[k]);
+__global__ __launch_bounds__(256) void em_march_kernel(EmLaunch L, EmPtrs<T> p, int ntx, int nty, int nkc, int kchunk,
+                                                       int acc_joule) {
+  __shared__ MarchSmem<T> S;
+  const int nb = ntx * nty * nkc;
+  const int b = xcd_remap(blockIdx.x, nb);
+  const int tx = b % ntx, ty = (b / ntx) % nty, kc = b / (ntx * nty);
+  em_march_tile<T, INC>(L, p, L.step, tx, ty, kc, kchunk, acc_joule, S);
 }
 
-// ---- block reductions (wave64 shuffles, then LDS across the 4 waves) -------
+// ---- batched: one launch walks the (variant, tile) list of all variants ----
+// Item = (variant, tile x, tile y, z chunk).  The step offset s is read from
+// device memory so that a captured chunk of steps can be replayed.
+template <typename T, bool INC>
+__global__ __launch_bounds__(256) void em_march_batched(const BatchVar *vars, const int4 *items, int n_items,
+                                                        const int64_t *step_ctr) {
+  __shared__ MarchSmem<T> S;
+  const int b = xcd_remap(blockIdx.x, n_items);
+  const int4 it = items[b];
+  const BatchVar &V = vars[it.x];
+  const int64_t s = *step_ctr;
+  const int64_t step = V.step0 + s;
+  EmPtrs<T> p;
+  if (INC) {
+    const int cur = int((V.cur0 + s) & 1), o = 1 - cur;
+    p.e = (const T *)V.e[cur][0];
+    p.aux = (const T *)V.d[cur][0];
+    p.oe = (T *)V.e[o][0];
+    p.oaux = (T *)V.d[o][0];
+  } else {
+    const int cur = int((V.cur0 + s) % 3), prv = (cur + 2) % 3, nxt = (cur + 1) % 3;
+    p.e = (const T *)V.e[cur][0];
+    p.aux = (const T *)V.e[prv][0];
+    p.oe = (T *)V.e[nxt][0];
+    p.oaux = nullptr;
+  }
+  const int acc = (s == 0) ? V.acc_joule0 : int(step % V.R != 0);
+  em_march_tile<T, INC>(V.L, p, step, it.y, it.z, it.w, V.kchunk, acc, S);
+}
+
+__global__ void step_ctr_kernel(int64_t *ctr, int64_t v, int set) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = set ? v : *ctr + v;
+}
+
+// ---- block reductions (wave64 shuffles, then LDS across the waves) --------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -258,8 +474,7 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 template <int NS, int NM>
-__device__ __forceinline__ void block_reduce_store(const double (&sums)[NS], const double (&maxs)[NM],
-                                                   double *out) {
+__device__ __forceinline__ void block_reduce_store(const double (&sums)[NS], const double (&maxs)[NM], double *out) {
   __shared__ double red[4][NS + NM];
   const int tid = threadIdx.x + threadIdx.y * blockDim.x;
   const int lane = tid & 63, wv = tid >> 6;
@@ -283,51 +498,124 @@ __device__ __forceinline__ void block_reduce_store(const double (&sums)[NS], con
   }
 }
 
-// ---- thermal step, Eq. (5) ---------------------------------------------------
+inline dim3 node_grid(const DevGrid &g) { return dim3((g.nx + 1 + BX - 1) / BX, (g.ny + 1 + BY - 1) / BY, g.nz + 1); }
+
+// Joule of the current field (the deferred last step) at node (i,j,k), with
+// the same arithmetic as the march kernel (missing low-side edges read 0).
+template <typename T>
+__device__ __forceinline__ double pending_joule(const DevGrid &g, const T *const *e, const T *cf, int i, int j, int k,
+                                                int64_t n, double jf) {
+  const double ax[2] = {g.al[0][i], g.ah[0][i]}, ay[2] = {g.al[1][j], g.ah[1][j]}, az[2] = {g.al[2][k], g.ah[2][k]};
+  const double v[6] = {double(e[0][n]), double(e[1][n]), double(e[2][n]), i > 0 ? double(e[0][n - 1]) : 0.0,
+                       j > 0 ? double(e[1][n - g.sy]) : 0.0, k > 0 ? double(e[2][n - g.sz]) : 0.0};
+  return joule_from_coef(cf, g.cs, uint32_t(n), uint32_t(g.sy), uint32_t(g.sz), i, j, k, ax, ay, az, v, jf);
+}
+
+// Per-node coefficients of the own x, y, z edges: eps_r and the normalised
+// material conductance a = dt sigma(T) / (2 eps0), formed in FP64 from the
+// cells around the node and stored at the field precision.
+template <typename T>
+__global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const T *th, T *cf) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i > g.nx || j > g.ny) return;
+  const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
+  const double ax[2] = {g.al[0][i], g.ah[0][i]}, ay[2] = {g.al[1][j], g.ah[1][j]}, az[2] = {g.al[2][k], g.ah[2][k]};
+  GCell CL{g.mat, g.mtab, n, g.sy, g.sz, i, j, k, g.nx, g.ny, g.nz};
+  GTcr TC{g.mtab};
+  GTh<T> TH{th, n, g.sy, g.sz};
+  double er[3], a[3];
+  a[0] = edge_coef<0>(1, ax, ay, az, CL, TC, TH, &er[0]);
+  a[1] = edge_coef<1>(1, ax, ay, az, CL, TC, TH, &er[1]);
+  a[2] = edge_coef<2>(1, ax, ay, az, CL, TC, TH, &er[2]);
+  const uint32_t cs = g.cs;
+  const uint8_t fl = g.flags[n];
+  for (int d = 0; d < 3; ++d) {
+    const double e = er[d] > 0.0 ? er[d] : 1.0;  // a missing edge keeps a harmless 1
+    if (sizeof(T) == 4) {
+      cf[d * cs + n] = T(1.0 / (e + a[d]));
+      cf[(3 + d) * cs + n] = T(2.0 * a[d]);
+    } else {
+      cf[d * cs + n] = T(e);
+      cf[(3 + d) * cs + n] = T(a[d]);
+    }
+    if (fl & (1 << d)) {
+      const int q = find_port(P, int64_t(d) * g.ntot + n);
+      if (q >= 0) P.er[q] = e;
+    }
+  }
+}
+
+// ---- thermal step, Eq. (5) ------------------------------------------------
 // C_n V_n (theta' - theta) = dt*psum*V_n - R*dt*sum_e G_e (theta_n - theta_m),
 // G_e = sum over the edge's cells of (quarter transverse area) k_c / L,
 // C_n V_n = sum over the node's cell octants of rho_cp * octant volume.
-__global__ __launch_bounds__(256) void thermal_kernel(ThermalLaunch L) {
+// The pending Joule power of the block's last EM step is added first, with
+// the conductivity of the temperature the block ran at.
+__device__ __forceinline__ void thermal_node(const ThermalLaunch &L, int i, int j, int k, int64_t n, double ps,
+                                             double &e_part, double &m_part) {
+  const DevGrid &g = L.g;
+  const double t0 = L.theta_in[n];
+  double CV = 0.0, gx0 = 0, gx1 = 0, gy0 = 0, gy1 = 0, gz0 = 0, gz1 = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+    const int ii = i - 1 + ox, jj = j - 1 + oy, kk = k - 1 + oz;
+    if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny || kk < 0 || kk >= g.nz) continue;
+    const double *row = g.mtab + g.mat[n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz] * kMatStride;
+    const double ddx = g.dx[ii], ddy = g.dy[jj], ddz = g.dz[kk], kc = row[MC_K];
+    CV += row[MC_RHOCP] * 0.125 * ddx * ddy * ddz;
+    const double wx = 0.25 * ddy * ddz * kc / ddx, wy = 0.25 * ddx * ddz * kc / ddy, wz = 0.25 * ddx * ddy * kc / ddz;
+    if (ox) gx1 += wx; else gx0 += wx;
+    if (oy) gy1 += wy; else gy0 += wy;
+    if (oz) gz1 += wz; else gz0 += wz;
+  }
+  double flux = 0.0;
+  if (i > 0) flux += gx0 * (t0 - L.theta_in[n - 1]);
+  if (i < g.nx) flux += gx1 * (t0 - L.theta_in[n + 1]);
+  if (j > 0) flux += gy0 * (t0 - L.theta_in[n - g.sy]);
+  if (j < g.ny) flux += gy1 * (t0 - L.theta_in[n + g.sy]);
+  if (k > 0) flux += gz0 * (t0 - L.theta_in[n - g.sz]);
+  if (k < g.nz) flux += gz1 * (t0 - L.theta_in[n + g.sz]);
+  const double V = g.hx[i] * g.hy[j] * g.hz[k];
+  const double tn = t0 + (L.dt * ps * V - double(L.R) * L.dt * flux) / CV;
+  L.theta_out[n] = tn;
+  L.psum[n] = 0.0;
+  if (L.theta32) L.theta32[n] = float(tn);
+  e_part = L.dt * ps * V;
+  m_part = tn;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void thermal_kernel(ThermalLaunch L, const T *e0, const T *e1, const T *e2,
+                                                      const T *cf) {
   const DevGrid &g = L.g;
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  double e_part = 0.0, m_part = 0.0;
+  double e_part = 0.0, m_part = -1.0e300;
   if (i <= g.nx && j <= g.ny) {
     const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
-    const double t0 = L.theta_in[n];
-    double CV = 0.0, gx0 = 0, gx1 = 0, gy0 = 0, gy1 = 0, gz0 = 0, gz1 = 0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-      const int ii = i - 1 + ox, jj = j - 1 + oy, kk = k - 1 + oz;
-      if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny || kk < 0 || kk >= g.nz) continue;
-      const double *row = g.mtab + g.mat[n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz] * kMatStride;
-      const double ddx = g.dx[ii], ddy = g.dy[jj], ddz = g.dz[kk], kc = row[MC_K];
-      CV += row[MC_RHOCP] * 0.125 * ddx * ddy * ddz;
-      // this cell touches the node's x-edge on side ox, y-edge on side oy, z-edge on side oz
-      const double wx = 0.25 * ddy * ddz * kc / ddx, wy = 0.25 * ddx * ddz * kc / ddy, wz = 0.25 * ddx * ddy * kc / ddz;
-      if (ox) gx1 += wx; else gx0 += wx;
-      if (oy) gy1 += wy; else gy0 += wy;
-      if (oz) gz1 += wz; else gz0 += wz;
+    double ps = L.psum[n];
+    if (L.acc_joule) {
+      const T *e[3] = {e0, e1, e2};
+      const double P = pending_joule<T>(g, e, cf, i, j, k, n, L.jf);
+      if (P != 0.0) ps += P;
     }
-    double flux = 0.0;
-    if (i > 0) flux += gx0 * (t0 - L.theta_in[n - 1]);
-    if (i < g.nx) flux += gx1 * (t0 - L.theta_in[n + 1]);
-    if (j > 0) flux += gy0 * (t0 - L.theta_in[n - g.sy]);
-    if (j < g.ny) flux += gy1 * (t0 - L.theta_in[n + g.sy]);
-    if (k > 0) flux += gz0 * (t0 - L.theta_in[n - g.sz]);
-    if (k < g.nz) flux += gz1 * (t0 - L.theta_in[n + g.sz]);
-    const double V = g.hx[i] * g.hy[j] * g.hz[k];
-    const double ps = L.psum[n];
-    const double tn = t0 + (L.dt * ps * V - double(L.R) * L.dt * flux) / CV;
-    L.theta_out[n] = tn;
-    L.psum[n] = 0.0;
-    if (L.theta32) L.theta32[n] = float(tn);
-    e_part = L.dt * ps * V;
-    m_part = tn;
+    thermal_node(L, i, j, k, n, ps, e_part, m_part);
   }
   const double s[1] = {e_part}, m[1] = {m_part};
   const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   block_reduce_store<1, 1>(s, m, L.partials + b * kRedWidth);
+}
+
+// Add the pending Joule power of the current field to psum.
+template <typename T>
+__global__ __launch_bounds__(256) void joule_flush_kernel(DevGrid g, const T *e0, const T *e1, const T *e2,
+                                                          const T *cf, double *psum, double jf) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i > g.nx || j > g.ny) return;
+  const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
+  const T *e[3] = {e0, e1, e2};
+  const double P = pending_joule<T>(g, e, cf, i, j, k, n, jf);
+  if (P != 0.0) psum[n] += P;
 }
 
 // Sum partials [nb][kRedWidth] in a fixed order (one block of 256).
@@ -371,30 +659,31 @@ __global__ __launch_bounds__(256) void diag_kernel(DiagLaunch L) {
     const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
     const T *en[3] = {(const T *)L.e_new[0], (const T *)L.e_new[1], (const T *)L.e_new[2]};
     const T *eo[3] = {(const T *)L.e_old[0], (const T *)L.e_old[1], (const T *)L.e_old[2]};
+    const double ax[2] = {g.al[0][i], g.ah[0][i]}, ay[2] = {g.al[1][j], g.ah[1][j]}, az[2] = {g.al[2][k], g.ah[2][k]};
+    GCell CL{g.mat, g.mtab, n, g.sy, g.sz, i, j, k, g.nx, g.ny, g.nz};
+    GTcr TC{g.mtab};
+    auto zero_th = [](int, int, int) { return 0.0; };
+    double er3[3];
+    (void)edge_coef<0>(1, ax, ay, az, CL, TC, zero_th, &er3[0]);
+    (void)edge_coef<1>(1, ax, ay, az, CL, TC, zero_th, &er3[1]);
+    (void)edge_coef<2>(1, ax, ay, az, CL, TC, zero_th, &er3[2]);
     double acc = 0.0;
     for (int D = 0; D < 3; ++D) {
       if ((D == 0 && i == g.nx) || (D == 1 && j == g.ny) || (D == 2 && k == g.nz)) continue;
       if (pec_edge(g, D, i, j, k)) continue;
       double cc;
       if (INC) {
-        LdDiff<T> ex{en[0], eo[0]}, ey{en[1], eo[1]}, ez{en[2], eo[2]};
-        cc = D == 0 ? double(curl_x<T>(g, ex, ey, ez, i, j, k, n)) : D == 1 ? double(curl_y<T>(g, ex, ey, ez, i, j, k, n))
-                                                                          : double(curl_z<T>(g, ex, ey, ez, i, j, k, n));
+        GDiff<T> E{{en[0], en[1], en[2]}, {eo[0], eo[1], eo[2]}, n, g.sy, g.sz};
+        cc = D == 0 ? double(curl_x<T>(g, E, i, j, k)) : D == 1 ? double(curl_y<T>(g, E, i, j, k)) : double(curl_z<T>(g, E, i, j, k));
       } else {
-        Ld1<T> ex{eo[0]}, ey{eo[1]}, ez{eo[2]};
-        cc = D == 0 ? double(curl_x<T>(g, ex, ey, ez, i, j, k, n)) : D == 1 ? double(curl_y<T>(g, ex, ey, ez, i, j, k, n))
-                                                                          : double(curl_z<T>(g, ex, ey, ez, i, j, k, n));
+        GAcc<T> E{{eo[0], eo[1], eo[2]}, n, g.sy, g.sz};
+        cc = D == 0 ? double(curl_x<T>(g, E, i, j, k)) : D == 1 ? double(curl_y<T>(g, E, i, j, k)) : double(curl_z<T>(g, E, i, j, k));
       }
-      double epsA, sigA;
-      if (D == 0) edge_sums<double, 0>(g, i, j, k, n, 0.0, epsA, sigA);
-      else if (D == 1) edge_sums<double, 1>(g, i, j, k, n, 0.0, epsA, sigA);
-      else edge_sums<double, 2>(g, i, j, k, n, 0.0, epsA, sigA);
       const double Lh = D == 0 ? g.dx[i] : D == 1 ? g.dy[j] : g.dz[k];
       const double A = D == 0 ? g.hy[j] * g.hz[k] : D == 1 ? g.hx[i] * g.hz[k] : g.hx[i] * g.hy[j];
       const double e1 = double(en[D][n]);
       const double dl = INC ? double(eo[D][n]) : e1 - double(eo[D][n]);
-      // er * L * A = epsA * L (epsA already carries the area)
-      acc += epsA * Lh * dl * dl + L.c2dt2 * Lh * A * e1 * cc;
+      acc += Lh * A * (er3[D] * dl * dl + L.c2dt2 * e1 * cc);
     }
     w_part = acc;
     j_part = L.psum[n] * (g.hx[i] * g.hy[j] * g.hz[k]);
@@ -429,8 +718,7 @@ __global__ __launch_bounds__(256) void diag_finalize(DiagLaunch L, int64_t nb) {
 }
 
 // ---- layout conversion and fills -------------------------------------------
-__global__ void pack_kernel(const void *src, int src_f32, int64_t sy, int64_t sz, int ni, int nj, int nk,
-                            double *dst) {
+__global__ void pack_kernel(const void *src, int src_f32, int64_t sy, int64_t sz, int ni, int nj, int nk, double *dst) {
   const int64_t total = int64_t(ni) * nj * nk;
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
     const int i = int(t % ni);
@@ -441,8 +729,7 @@ __global__ void pack_kernel(const void *src, int src_f32, int64_t sy, int64_t sz
   }
 }
 
-__global__ void unpack_kernel(const double *src, int ni, int nj, int nk, void *dst, int dst_f32, int64_t sy,
-                              int64_t sz) {
+__global__ void unpack_kernel(const double *src, int ni, int nj, int nk, void *dst, int dst_f32, int64_t sy, int64_t sz) {
   const int64_t total = int64_t(ni) * nj * nk;
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
     const int i = int(t % ni);
@@ -458,43 +745,90 @@ __global__ void fill_kernel(uint32_t *dst, int64_t n_words) {
     dst[t] = 0u;
 }
 
-inline dim3 node_grid(const DevGrid &g) {
-  return dim3((g.nx + 1 + BX - 1) / BX, (g.ny + 1 + BY - 1) / BY, g.nz + 1);
-}
-
 }  // namespace
 
-int reduce_blocks(int64_t) { return 0; }
+void em_tiles(const DevGrid &g, int kchunk, int *ntx, int *nty, int *nkc) {
+  *ntx = (g.nx + 1 + BX - 1) / BX;
+  *nty = (g.ny + 1 + BY - 1) / BY;
+  *nkc = (g.nz + 1 + kchunk - 1) / kchunk;
+}
+
+int em_kchunk(const DevGrid &g) {
+  // Enough blocks to fill 256 CUs several times over, with chunks long
+  // enough that the two extra planes staged per chunk stay cheap.
+  int ntx, nty, nkc;
+  em_tiles(g, 1, &ntx, &nty, &nkc);
+  const int64_t cols = int64_t(ntx) * nty;
+  int kc = 16;
+  while (kc > 4 && cols * ((g.nz + 1 + kc - 1) / kc) < 2048) kc /= 2;
+  return kc;
+}
 
 hipError_t launch_em_step(const EmLaunch &L, hipStream_t s) {
-  const dim3 grid = node_grid(L.g), block(BX, BY, 1);
+  int ntx, nty, nkc;
+  const int kc = L.kchunk > 0 ? L.kchunk : em_kchunk(L.g);
+  em_tiles(L.g, kc, &ntx, &nty, &nkc);
+  const int nb = ntx * nty * nkc;
+  const dim3 block(BX, BY, 1);
   if (L.precision == ETM_PREC_FP64) {
-    EmPtrs<double> p;
-    for (int d = 0; d < 3; ++d) {
-      p.e[d] = (const double *)L.e0[d];
-      p.aux[d] = (const double *)L.e1[d];
-      p.oe[d] = (double *)L.out0[d];
-      p.oaux[d] = nullptr;
-    }
-    hipLaunchKernelGGL((em_step_kernel<double, false>), grid, block, 0, s, L, p, L.theta);
+    EmPtrs<double> p{(const double *)L.e0[0], (const double *)L.e1[0], (double *)L.out0[0], nullptr};
+    hipLaunchKernelGGL((em_march_kernel<double, false>), dim3(nb), block, 0, s, L, p, ntx, nty, nkc, kc, L.acc_joule);
   } else {
-    EmPtrs<float> p;
-    for (int d = 0; d < 3; ++d) {
-      p.e[d] = (const float *)L.e0[d];
-      p.aux[d] = (const float *)L.e1[d];
-      p.oe[d] = (float *)L.out0[d];
-      p.oaux[d] = (float *)L.out1[d];
-    }
-    hipLaunchKernelGGL((em_step_kernel<float, true>), grid, block, 0, s, L, p, L.theta32);
+    EmPtrs<float> p{(const float *)L.e0[0], (const float *)L.e1[0], (float *)L.out0[0], (float *)L.out1[0]};
+    hipLaunchKernelGGL((em_march_kernel<float, true>), dim3(nb), block, 0, s, L, p, ntx, nty, nkc, kc, L.acc_joule);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_em_batched(const BatchVar *vars, const int4 *items, int n_items, const int64_t *step_ctr,
+                             int precision, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  if (precision == ETM_PREC_FP64)
+    hipLaunchKernelGGL((em_march_batched<double, false>), dim3(n_items), dim3(BX, BY), 0, st, vars, items, n_items,
+                       step_ctr);
+  else
+    hipLaunchKernelGGL((em_march_batched<float, true>), dim3(n_items), dim3(BX, BY), 0, st, vars, items, n_items,
+                       step_ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_ctr(int64_t *ctr, int64_t v, int set, hipStream_t s) {
+  hipLaunchKernelGGL(step_ctr_kernel, dim3(1), dim3(64), 0, s, ctr, v, set);
   return hipGetLastError();
 }
 
 hipError_t launch_thermal(const ThermalLaunch &L, hipStream_t s) {
   const dim3 grid = node_grid(L.g), block(BX, BY, 1);
-  hipLaunchKernelGGL(thermal_kernel, grid, block, 0, s, L);
+  if (L.precision == ETM_PREC_FP64)
+    hipLaunchKernelGGL((thermal_kernel<double>), grid, block, 0, s, L, (const double *)L.e[0], (const double *)L.e[1],
+                       (const double *)L.e[2], (const double *)L.coef);
+  else
+    hipLaunchKernelGGL((thermal_kernel<float>), grid, block, 0, s, L, (const float *)L.e[0], (const float *)L.e[1],
+                       (const float *)L.e[2], (const float *)L.coef);
   const int64_t nb = int64_t(grid.x) * grid.y * grid.z;
   hipLaunchKernelGGL(thermal_finalize, dim3(1), dim3(256), 0, s, (const double *)L.partials, nb, L.sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_joule_flush(const DevGrid &g, int precision, const void *const *e, const void *coef, double *psum,
+                              double jf, hipStream_t s) {
+  const dim3 grid = node_grid(g), block(BX, BY, 1);
+  if (precision == ETM_PREC_FP64)
+    hipLaunchKernelGGL((joule_flush_kernel<double>), grid, block, 0, s, g, (const double *)e[0], (const double *)e[1],
+                       (const double *)e[2], (const double *)coef, psum, jf);
+  else
+    hipLaunchKernelGGL((joule_flush_kernel<float>), grid, block, 0, s, g, (const float *)e[0], (const float *)e[1],
+                       (const float *)e[2], (const float *)coef, psum, jf);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef(const DevGrid &g, const DevPorts &P, int precision, const void *theta, void *coef,
+                       hipStream_t s) {
+  const dim3 grid = node_grid(g), block(BX, BY, 1);
+  if (precision == ETM_PREC_FP64)
+    hipLaunchKernelGGL((coef_kernel<double>), grid, block, 0, s, g, P, (const double *)theta, (double *)coef);
+  else
+    hipLaunchKernelGGL((coef_kernel<float>), grid, block, 0, s, g, P, (const float *)theta, (float *)coef);
   return hipGetLastError();
 }
 

@@ -43,6 +43,9 @@ struct DevGrid {
   const double *idx, *idy, *idz;  // 1 / width
   const double *hx, *hy, *hz;     // node-centred widths (half cells at the ends)
   const double *ihx, *ihy, *ihz;  // 1 / node-centred width
+  const double *al[3], *ah[3];    // per axis: alpha_lo, alpha_hi on nodes (dual-width shares)
+  const double *geo;              // base of all 1D tables (dx, dy, dz, idx, ..., ihz, axl, axh, ..., azh)
+  uint32_t cs;                    // element stride between the x, y, z components of a field (march kernel)
   const uint8_t *mat;             // cell material ids
   const uint8_t *flags;           // per node: bit d = the d-edge from this node is a port edge
   const double *mtab;             // n_mat rows of kMatStride
@@ -61,6 +64,7 @@ struct DevPorts {
   const double *wt;
   const double *J;    // [n_waves][n_samples]
   int64_t n_samples;
+  double *er;         // eps_r of each port edge (written by the coefficient kernel)
 };
 
 // Scalars kept on the device for a plan.
@@ -84,11 +88,14 @@ struct EmLaunch {
   DevGrid g;
   DevPorts ports;
   int precision;          // ETM_PREC_FP64 / ETM_PREC_MIXED
+  int acc_joule;          // add the Joule power of the input field e^n to psum
+  int kchunk;             // z planes per block (0 = automatic)
+  int pad0;
   double c2dt2;           // (c0 dt)^2
   double jf;              // eps0 / dt: Joule factor on e^2 * L * sigma_s-area sums
   int64_t step;           // n of the step being made (e^{n} -> e^{n+1})
   // FP64: e0 = e^n, e1 = e^{n-1}, out = e^{n+1}
-  // MIXED: e0 = e^n (float), d0 = delta^{n-1/2}, out_e / out_d
+  // MIXED: e0 = e^n (float), e1 = delta^{n-1/2}, out0 / out1 = e^{n+1}, delta^{n+1/2}
   const void *e0[3];
   const void *e1[3];
   void *out0[3];
@@ -96,21 +103,54 @@ struct EmLaunch {
   const double *theta;    // FP64 rise (FP64 path)
   const float *theta32;   // FP32 copy (mixed path)
   double *psum;
+  const void *coef;       // per node, 6 components at stride cs (see launch_coef)
 };
 hipError_t launch_em_step(const EmLaunch &L, hipStream_t s);
+// Refresh the per-node coefficients of the own x, y, z edges for the current
+// temperature (FP64 arithmetic, rounded once to the field precision):
+//   FP64:  [eps_r x, y, z, a x, y, z]
+//   mixed: [1/(eps_r + a) x, y, z, 2a x, y, z]
+// with a = dt sigma(T) / (2 eps0) of the materials (port conductances are
+// added in the march); also the eps_r of every port edge.
+hipError_t launch_coef(const DevGrid &g, const DevPorts &P, int precision, const void *theta, void *coef,
+                       hipStream_t s);
+void em_tiles(const DevGrid &g, int kchunk, int *ntx, int *nty, int *nkc);
+int em_kchunk(const DevGrid &g);
+
+// One variant of a batch: its grid, constants and state buffers; the step
+// offset within the advance call is read from a device counter.
+struct BatchVar {
+  EmLaunch L;             // grid, ports, constants and psum (field pointers unused)
+  const void *e[3][3];    // FP64: three rotating e buffers; MIXED: sets 0..1
+  const void *d[2][3];    // MIXED: delta sets
+  const double *theta[2];
+  const float *theta32;
+  int64_t step0;          // plan step at the start of the advance call
+  int cur0, th0, R, kchunk, acc_joule0, pad1;
+};
+hipError_t launch_em_batched(const BatchVar *vars, const int4 *items, int n_items, const int64_t *step_ctr,
+                             int precision, hipStream_t s);
+hipError_t launch_step_ctr(int64_t *ctr, int64_t v, int set, hipStream_t s);
 
 struct ThermalLaunch {
   DevGrid g;
+  const void *coef;       // edge coefficients (for the pending Joule power)
+  int precision;
+  int acc_joule;          // add the pending Joule power of the current field first
   double dt;              // EM step
+  double jf;
   int R;                  // EM steps in the block
+  const void *e[3];       // current field (for the pending Joule power)
   const double *theta_in;
   double *theta_out;
-  float *theta32;         // refreshed copy (may be null)
+  float *theta32;         // refreshed copy (mixed path; also its sigma(T) input)
   double *psum;           // zeroed
   double *partials;       // per block: [energy, max]
   DevScalars *sc;
 };
 hipError_t launch_thermal(const ThermalLaunch &L, hipStream_t s);
+hipError_t launch_joule_flush(const DevGrid &g, int precision, const void *const *e, const void *coef, double *psum,
+                              double jf, hipStream_t s);
 
 struct DiagLaunch {
   DevGrid g;

@@ -12,125 +12,19 @@
 #include <vector>
 
 #include "etm_internal.h"
+#include "plan.h"
 
 using namespace etm;
 
+namespace etm {
 namespace {
-
 thread_local std::string g_err;
-
+}  // namespace
 etm_status fail(etm_status s, const std::string &msg) {
   g_err = msg;
   return s;
 }
-
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess) return fail(ETM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-struct Region {
-  size_t off = 0, bytes = 0;
-};
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-}  // namespace
-
-struct etm_plan {
-  // ---- inputs (deep copies)
-  int nx = 0, ny = 0, nz = 0, n_mat = 0;
-  std::vector<double> dx, dy, dz;
-  std::vector<uint8_t> mat_nat;
-  std::vector<etm_material> mats;
-  int n_waves = 0;
-  int64_t n_samples = 0;
-  std::vector<double> J;
-  etm_opts opts{};
-  double dt = 0;
-  int prec = ETM_PREC_FP64, R = 1;
-  // ---- layout
-  int64_t sy = 0, sz = 0, ntot = 0;
-  dim3 ngrid;
-  int64_t nblocks_node = 0;
-  // ---- host tables
-  std::vector<double> geo;  // dx,dy,dz,idx,idy,idz (n each), hx,hy,hz,ihx,ihy,ihz (n+1 each)
-  size_t geo_off[12] = {};
-  std::vector<double> mtab;
-  std::vector<uint8_t> mat_pad, flags, fixed;
-  std::vector<int64_t> pe_key;
-  std::vector<double> pe_gs, pw_wt;
-  std::vector<int32_t> pe_start, pw_wave;
-  std::vector<int64_t> probes_dev;  // [field, padded index]
-  int64_t hist_cap = 0;
-  int hist_cols = 4;
-  // ---- workspace regions
-  Region r_geo, r_mtab, r_mat, r_flags, r_fixed, r_pkey, r_pgs, r_pstart, r_pwave, r_pwt, r_J, r_probes;
-  Region r_e[3][3];     // FP64: three rotating e buffers;  MIXED: [0..1] e sets, [2] unused
-  Region r_d[2][3];     // MIXED: delta sets
-  Region r_theta[2], r_theta32, r_psum, r_part, r_sc, r_hist;
-  Region r_u64[3], r_f64[3], r_r64[3], r_p64[3], r_w64[3], r_dinv64[3];
-  Region r_u32[3], r_r32[3], r_p32[3], r_w32[3], r_dinv32[3], r_rhs32[3];
-  Region r_vm, r_stage;
-  size_t footprint = 0;
-  // ---- bound state
-  char *ws = nullptr;
-  hipStream_t stream = nullptr;
-  bool bound = false;
-  DevScalars *sc_host = nullptr;  // pinned
-  int64_t step = 0;
-  int cur = 0;      // FP64: e^n = buffer cur; MIXED: set cur
-  int th_cur = 0;
-  int64_t rec = 0;
-  int64_t n_thermal = 0;
-  int n_solves = 0, cg_iters = 0, cg_outer = 0;
-  int64_t cg_total = 0;
-  double cg_relres = 0;
-  etm_status host_status = ETM_OK;
-  bool dinv_ready = false;
-
-  template <typename T>
-  T *ptr(const Region &r) const { return reinterpret_cast<T *>(ws + r.off); }
-
-  DevGrid dev_grid() const {
-    DevGrid g;
-    g.nx = nx; g.ny = ny; g.nz = nz; g.n_mat = n_mat;
-    g.sy = sy; g.sz = sz; g.ntot = ntot;
-    const double *gb = ptr<double>(r_geo);
-    g.dx = gb + geo_off[0]; g.dy = gb + geo_off[1]; g.dz = gb + geo_off[2];
-    g.idx = gb + geo_off[3]; g.idy = gb + geo_off[4]; g.idz = gb + geo_off[5];
-    g.hx = gb + geo_off[6]; g.hy = gb + geo_off[7]; g.hz = gb + geo_off[8];
-    g.ihx = gb + geo_off[9]; g.ihy = gb + geo_off[10]; g.ihz = gb + geo_off[11];
-    g.mat = ptr<uint8_t>(r_mat);
-    g.flags = ptr<uint8_t>(r_flags);
-    g.mtab = ptr<double>(r_mtab);
-    int pec = 0;
-    for (int f = 0; f < 6; ++f) if (opts.em_bc[f] == ETM_PEC) pec |= 1 << f;
-    g.pec = pec;
-    return g;
-  }
-  DevPorts dev_ports() const {
-    DevPorts p;
-    p.n_edges = int(pe_key.size());
-    p.key = ptr<int64_t>(r_pkey);
-    p.gs = ptr<double>(r_pgs);
-    p.start = ptr<int32_t>(r_pstart);
-    p.wave = ptr<int32_t>(r_pwave);
-    p.wt = ptr<double>(r_pwt);
-    p.J = ptr<double>(r_J);
-    p.n_samples = n_samples;
-    return p;
-  }
-  MechGrid mech_grid() const {
-    MechGrid m;
-    m.g = dev_grid();
-    m.fixed = ptr<uint8_t>(r_fixed);
-    return m;
-  }
-  DevScalars *sc() const { return ptr<DevScalars>(r_sc); }
-  int64_t nidx(int i, int j, int k) const { return int64_t(k) * sz + int64_t(j) * sy + i; }
-};
+}  // namespace etm
 
 namespace {
 
@@ -238,8 +132,22 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   p->nblocks_node = int64_t(p->ngrid.x) * p->ngrid.y * p->ngrid.z;
   // geometry table
   const std::vector<double> hx = dual(p->dx), hy = dual(p->dy), hz = dual(p->dz);
-  const std::vector<double> *parts[12];
+  const std::vector<double> *parts[18];
   std::vector<double> idx(nx), idy(ny), idz(nz), ihx(nx + 1), ihy(ny + 1), ihz(nz + 1);
+  // Share of a node's dual width on each side: alpha_lo(i) = dx[i-1] / (2 hx[i]),
+  // alpha_hi(i) = dx[i] / (2 hx[i]) (0 for a missing cell).  Products of two
+  // of them are the area weights of an edge's (up to four) cells.
+  auto alphas = [](const std::vector<double> &d, const std::vector<double> &h, std::vector<double> &lo,
+                   std::vector<double> &hi) {
+    const size_t n = d.size();
+    lo.assign(n + 1, 0.0);
+    hi.assign(n + 1, 0.0);
+    for (size_t q = 0; q <= n; ++q) {
+      if (q > 0) lo[q] = d[q - 1] / (2.0 * h[q]);
+      if (q < n) hi[q] = d[q] / (2.0 * h[q]);
+    }
+  };
+  std::vector<double> axl, axh, ayl, ayh, azl, azh;
   for (int i = 0; i < nx; ++i) idx[i] = 1.0 / p->dx[i];
   for (int j = 0; j < ny; ++j) idy[j] = 1.0 / p->dy[j];
   for (int k = 0; k < nz; ++k) idz[k] = 1.0 / p->dz[k];
@@ -250,8 +158,12 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   parts[3] = &idx; parts[4] = &idy; parts[5] = &idz;
   parts[6] = &hx; parts[7] = &hy; parts[8] = &hz;
   parts[9] = &ihx; parts[10] = &ihy; parts[11] = &ihz;
+  alphas(p->dx, hx, axl, axh);
+  alphas(p->dy, hy, ayl, ayh);
+  alphas(p->dz, hz, azl, azh);
+  parts[12] = &axl; parts[13] = &axh; parts[14] = &ayl; parts[15] = &ayh; parts[16] = &azl; parts[17] = &azh;
   p->geo.clear();
-  for (int q = 0; q < 12; ++q) {
+  for (int q = 0; q < 18; ++q) {
     p->geo_off[q] = p->geo.size();
     p->geo.insert(p->geo.end(), parts[q]->begin(), parts[q]->end());
   }
@@ -287,6 +199,13 @@ etm_status derive(etm_plan *p, const etm_source *src) {
     const double lam = 4.0 * dmax * (1 / (mx * mx) + 1 / (my * my) + 1 / (mz * mz));
     if (p->R * p->dt * lam > 2.0 && !p->opts.force_dt)
       return fail(ETM_E_UNSTABLE, "thermal step R*dt exceeds the forward-Euler bound");
+  }
+  {
+    std::vector<char> used(p->n_mat, 0);
+    for (uint8_t m : p->mat_nat) used[m] = 1;
+    p->has_tcr = false;
+    for (int m = 0; m < p->n_mat; ++m)
+      if (used[m] && p->mats[m].tcr != 0.0 && p->mats[m].sigma0 != 0.0) p->has_tcr = true;
   }
   // padded cell ids
   p->mat_pad.assign(p->ntot, 0);
@@ -395,8 +314,10 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   take(p->r_pstart, p->pe_start.size() * 4);
   take(p->r_pwave, p->pw_wave.size() * 4);
   take(p->r_pwt, p->pw_wt.size() * 8);
+  take(p->r_per, p->pe_key.size() * 8);
   take(p->r_J, p->J.size() * 8);
   take(p->r_probes, p->probes_dev.size() * 8);
+  for (int c = 0; c < 6; ++c) take(p->r_coef[c], N * (p->prec == ETM_PREC_FP64 ? 8 : 4));
   if (p->prec == ETM_PREC_FP64) {
     for (int b = 0; b < 3; ++b) for (int c = 0; c < 3; ++c) take(p->r_e[b][c], N * 8);
   } else {
@@ -424,6 +345,23 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   take(p->r_vm, N * 8);
   take(p->r_stage, N * 8);
   p->footprint = off;
+  // the march kernel addresses the x, y, z components of a field from one
+  // base with a fixed stride: check the layout gives one
+  {
+    const size_t esz = p->prec == ETM_PREC_FP64 ? 8 : 4;
+    p->comp_stride = int64_t((p->r_e[0][1].off - p->r_e[0][0].off) / esz);
+    for (int b = 0; b < (p->prec == ETM_PREC_FP64 ? 3 : 2); ++b)
+      for (int c = 1; c < 3; ++c)
+        if (p->r_e[b][c].off - p->r_e[b][c - 1].off != size_t(p->comp_stride) * esz) return fail(ETM_E_INVAL, "layout");
+    if (p->prec == ETM_PREC_MIXED)
+      for (int b = 0; b < 2; ++b)
+        for (int c = 1; c < 3; ++c)
+          if (p->r_d[b][c].off - p->r_d[b][c - 1].off != size_t(p->comp_stride) * esz) return fail(ETM_E_INVAL, "layout");
+    for (int c = 1; c < 6; ++c)
+      if (p->r_coef[c].off - p->r_coef[c - 1].off != size_t(p->comp_stride) * esz) return fail(ETM_E_INVAL, "layout");
+    if (p->ntot + 2 * p->comp_stride >= (int64_t(1) << 32))
+      return fail(ETM_E_INVAL, "mesh too large for 32-bit node offsets (padded nodes must stay below 1.4e9)");
+  }
   return ETM_OK;
 }
 
@@ -461,17 +399,12 @@ const void *field_ptr(const etm_plan *p, int field, int *is_f32) {
   return nullptr;
 }
 
-etm_status em_one_step(etm_plan *p) {
-  EmLaunch L;
-  L.g = p->dev_grid();
-  L.ports = p->dev_ports();
-  L.precision = p->prec;
-  L.c2dt2 = (kC0 * p->dt) * (kC0 * p->dt);
-  L.jf = kEps0 / p->dt;
-  L.step = p->step;
-  L.theta = p->ptr<double>(p->r_theta[p->th_cur]);
-  L.theta32 = p->prec == ETM_PREC_MIXED ? p->ptr<float>(p->r_theta32) : nullptr;
-  L.psum = p->ptr<double>(p->r_psum);
+}  // namespace
+
+namespace etm {
+
+// Pointers of the current / previous / next e state.
+static void em_pointers(const etm_plan *p, EmLaunch &L) {
   if (p->prec == ETM_PREC_FP64) {
     const int c = p->cur, prv = (c + 2) % 3, nxt = (c + 1) % 3;
     for (int d = 0; d < 3; ++d) {
@@ -489,11 +422,70 @@ etm_status em_one_step(etm_plan *p) {
       L.out1[d] = p->ws + p->r_d[o][d].off;
     }
   }
+}
+
+EmLaunch em_launch_template(const etm_plan *p) {
+  EmLaunch L;
+  std::memset(&L, 0, sizeof(L));
+  L.g = p->dev_grid();
+  L.ports = p->dev_ports();
+  L.precision = p->prec;
+  L.kchunk = p->kchunk;
+  L.c2dt2 = (kC0 * p->dt) * (kC0 * p->dt);
+  L.jf = kEps0 / p->dt;
+  L.step = p->step;
+  L.theta = p->ptr<double>(p->r_theta[p->th_cur]);
+  L.theta32 = p->prec == ETM_PREC_MIXED ? p->ptr<float>(p->r_theta32) : nullptr;
+  L.psum = p->ptr<double>(p->r_psum);
+  L.g.cs = uint32_t(p->comp_stride);
+  L.coef = p->ws + p->r_coef[0].off;
+  return L;
+}
+
+// Edge coefficients for the current temperature.
+etm_status coef_refresh(etm_plan *p) {
+  DevGrid g = p->dev_grid();
+  g.cs = uint32_t(p->comp_stride);
+  const void *th = p->prec == ETM_PREC_MIXED ? (const void *)p->ptr<float>(p->r_theta32)
+                                             : (const void *)p->ptr<double>(p->r_theta[p->th_cur]);
+  HIP_TRY(launch_coef(g, p->dev_ports(), p->prec, th, p->ws + p->r_coef[0].off, p->stream));
+  return ETM_OK;
+}
+
+// One EM step e^n -> e^{n+1}; the Joule power of e^n is added to the block
+// sum when it is still pending.
+etm_status em_one_step(etm_plan *p) {
+  EmLaunch L = em_launch_template(p);
+  L.acc_joule = p->joule_pending ? 1 : 0;
+  em_pointers(p, L);
   HIP_TRY(launch_em_step(L, p->stream));
+  p->cur = p->prec == ETM_PREC_FP64 ? (p->cur + 1) % 3 : 1 - p->cur;
+  p->step++;
+  p->joule_pending = true;
+  return ETM_OK;
+}
+
+static void current_e(const etm_plan *p, const void *e[3]) {
+  for (int d = 0; d < 3; ++d) e[d] = p->ws + p->r_e[p->cur][d].off;
+}
+
+// Add the Joule power of the current field to the block sum (so that the
+// sum is complete whenever the host can look at it).
+etm_status joule_flush(etm_plan *p) {
+  if (!p->joule_pending) return ETM_OK;
+  const void *e[3];
+  current_e(p, e);
+  DevGrid g = p->dev_grid();
+  g.cs = uint32_t(p->comp_stride);
+  HIP_TRY(launch_joule_flush(g, p->prec, e, p->ws + p->r_coef[0].off, p->ptr<double>(p->r_psum), kEps0 / p->dt,
+                             p->stream));
+  p->joule_pending = false;
   return ETM_OK;
 }
 
 etm_status diag_record(etm_plan *p, int old_cur) {
+  etm_status st = joule_flush(p);
+  if (st != ETM_OK) return st;
   // after the step: new state is p->cur, old is old_cur
   DiagLaunch D;
   D.g = p->dev_grid();
@@ -523,19 +515,29 @@ etm_status diag_record(etm_plan *p, int old_cur) {
 etm_status thermal_one(etm_plan *p) {
   ThermalLaunch T;
   T.g = p->dev_grid();
+  T.precision = p->prec;
+  T.acc_joule = p->joule_pending ? 1 : 0;
   T.dt = p->dt;
+  T.jf = kEps0 / p->dt;
   T.R = p->R;
+  current_e(p, T.e);
   T.theta_in = p->ptr<double>(p->r_theta[p->th_cur]);
   T.theta_out = p->ptr<double>(p->r_theta[1 - p->th_cur]);
   T.theta32 = p->prec == ETM_PREC_MIXED ? p->ptr<float>(p->r_theta32) : nullptr;
   T.psum = p->ptr<double>(p->r_psum);
   T.partials = p->ptr<double>(p->r_part);
   T.sc = p->sc();
+  T.g.cs = uint32_t(p->comp_stride);
+  T.coef = p->ws + p->r_coef[0].off;
   HIP_TRY(launch_thermal(T, p->stream));
   p->th_cur = 1 - p->th_cur;
   p->n_thermal++;
+  p->joule_pending = false;
+  if (p->has_tcr) return coef_refresh(p);
   return ETM_OK;
 }
+
+namespace {
 
 etm_status poll_scalars(etm_plan *p) {
   HIP_TRY(hipMemcpyAsync(p->sc_host, p->sc(), sizeof(DevScalars), hipMemcpyDeviceToHost, p->stream));
@@ -567,6 +569,8 @@ etm_status run_cg(etm_plan *p, const MechGrid &M, const CgVecs<T> &v, const T *r
   }
   return ETM_OK;
 }
+
+}  // namespace
 
 etm_status mech_solve_impl(etm_plan *p) {
   etm_status st;
@@ -658,7 +662,7 @@ etm_status mech_solve_impl(etm_plan *p) {
   return ETM_OK;
 }
 
-}  // namespace
+}  // namespace etm
 
 // =============================== C ABI ======================================
 extern "C" {
@@ -757,12 +761,14 @@ etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
       (st = up(p->r_J, p->J.data(), p->J.size() * 8)) ||
       (st = up(p->r_probes, p->probes_dev.data(), p->probes_dev.size() * 8)))
     return st;
-  HIP_TRY(hipStreamSynchronize(p->stream));
   p->bound = true;
+  if ((st = coef_refresh(p)) != ETM_OK) return st;
+  HIP_TRY(hipStreamSynchronize(p->stream));
   p->step = 0; p->cur = 0; p->th_cur = 0; p->rec = 0; p->n_thermal = 0;
   p->n_solves = 0; p->cg_iters = 0; p->cg_outer = 0; p->cg_total = 0; p->cg_relres = 0;
   p->host_status = ETM_OK;
   p->dinv_ready = false;
+  p->joule_pending = false;
   return ETM_OK;
 }
 
@@ -774,8 +780,6 @@ etm_status etm_advance(etm_plan *p, int64_t n) {
   for (int64_t q = 0; q < n; ++q) {
     const int old = p->cur;
     if ((st = em_one_step(p)) != ETM_OK) return st;
-    p->cur = p->prec == ETM_PREC_FP64 ? (p->cur + 1) % 3 : 1 - p->cur;
-    p->step++;
     if (p->step % p->R == 0) {
       if ((st = thermal_one(p)) != ETM_OK) return st;
       if (p->opts.mech_every_thermal > 0 && p->n_thermal % p->opts.mech_every_thermal == 0) {
@@ -786,7 +790,7 @@ etm_status etm_advance(etm_plan *p, int64_t n) {
     if (p->opts.history_stride > 0 && p->step % p->opts.history_stride == 0)
       if ((st = diag_record(p, old)) != ETM_OK) return st;
   }
-  return ETM_OK;
+  return joule_flush(p);
 }
 
 etm_status etm_mech_solve(etm_plan *p) {
@@ -878,6 +882,10 @@ etm_status etm_write(etm_plan *p, int32_t field, const void *src, size_t bytes, 
   HIP_TRY(launch_unpack(stage, fd.ni, fd.nj, fd.nk, dstp, f32, p->sy, p->sz, p->stream));
   if (field == ETM_FIELD_THETA && p->prec == ETM_PREC_MIXED)
     HIP_TRY(launch_unpack(stage, fd.ni, fd.nj, fd.nk, p->ptr<float>(p->r_theta32), 1, p->sy, p->sz, p->stream));
+  if (field == ETM_FIELD_THETA && p->has_tcr) {
+    etm_status st = coef_refresh(p);
+    if (st != ETM_OK) return st;
+  }
   if (field >= ETM_FIELD_UX && field <= ETM_FIELD_UZ) {
     // keep fixed DOFs at zero
     std::vector<double> h(need / 8);
@@ -970,7 +978,8 @@ etm_status etm_restore(etm_plan *p, const void *src, size_t bytes) {
   p->step = h.step; p->rec = h.rec; p->n_thermal = h.n_thermal; p->cg_total = h.cg_total;
   p->cur = h.cur; p->th_cur = h.th_cur; p->n_solves = h.n_solves;
   p->host_status = ETM_OK;
-  return ETM_OK;
+  p->joule_pending = false;
+  return coef_refresh(p);
 }
 
 void etm_plan_destroy(etm_plan *p) {

@@ -1,0 +1,142 @@
+// Private host-side plan of the library (shared by plan.cpp and batch.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "etm_internal.h"
+
+namespace etm {
+etm_status fail(etm_status s, const std::string &msg);
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace etm
+
+#define HIP_TRY(expr)                                                                                      \
+  do {                                                                                                     \
+    hipError_t e_ = (expr);                                                                                \
+    if (e_ != hipSuccess) return etm::fail(ETM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+
+
+using namespace etm;
+
+struct etm_plan {
+  // ---- inputs (deep copies)
+  int nx = 0, ny = 0, nz = 0, n_mat = 0;
+  std::vector<double> dx, dy, dz;
+  std::vector<uint8_t> mat_nat;
+  std::vector<etm_material> mats;
+  int n_waves = 0;
+  int64_t n_samples = 0;
+  std::vector<double> J;
+  etm_opts opts{};
+  double dt = 0;
+  int prec = ETM_PREC_FP64, R = 1;
+  // ---- layout
+  int64_t sy = 0, sz = 0, ntot = 0;
+  dim3 ngrid;
+  int64_t nblocks_node = 0;
+  // ---- host tables
+  std::vector<double> geo;  // dx,dy,dz,idx,idy,idz (n each), hx,hy,hz,ihx,ihy,ihz (n+1 each)
+  size_t geo_off[18] = {};
+  std::vector<double> mtab;
+  std::vector<uint8_t> mat_pad, flags, fixed;
+  std::vector<int64_t> pe_key;
+  std::vector<double> pe_gs, pw_wt;
+  std::vector<int32_t> pe_start, pw_wave;
+  std::vector<int64_t> probes_dev;  // [field, padded index]
+  int64_t hist_cap = 0;
+  int hist_cols = 4;
+  // ---- workspace regions
+  Region r_geo, r_mtab, r_mat, r_flags, r_fixed, r_pkey, r_pgs, r_pstart, r_pwave, r_pwt, r_J, r_probes, r_per;
+  Region r_coef[6];     // per-node edge coefficients: eps_r x/y/z, a x/y/z (field precision)
+  Region r_e[3][3];     // FP64: three rotating e buffers;  MIXED: [0..1] e sets, [2] unused
+  Region r_d[2][3];     // MIXED: delta sets
+  Region r_theta[2], r_theta32, r_psum, r_part, r_sc, r_hist;
+  Region r_u64[3], r_f64[3], r_r64[3], r_p64[3], r_w64[3], r_dinv64[3];
+  Region r_u32[3], r_r32[3], r_p32[3], r_w32[3], r_dinv32[3], r_rhs32[3];
+  Region r_vm, r_stage;
+  size_t footprint = 0;
+  // ---- bound state
+  char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  DevScalars *sc_host = nullptr;  // pinned
+  int64_t step = 0;
+  int cur = 0;      // FP64: e^n = buffer cur; MIXED: set cur
+  int th_cur = 0;
+  int64_t rec = 0;
+  int64_t n_thermal = 0;
+  int n_solves = 0, cg_iters = 0, cg_outer = 0;
+  int64_t cg_total = 0;
+  double cg_relres = 0;
+  etm_status host_status = ETM_OK;
+  bool dinv_ready = false;
+  bool joule_pending = false;  // Joule power of the current field not yet in psum
+  int kchunk = 0;              // z planes per EM block (0 = automatic)
+  int64_t comp_stride = 0;     // elements between the x, y, z components of a field
+  bool has_tcr = false;        // some conducting material has a temperature coefficient
+
+  template <typename T>
+  T *ptr(const Region &r) const { return reinterpret_cast<T *>(ws + r.off); }
+
+  DevGrid dev_grid() const {
+    DevGrid g;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.n_mat = n_mat;
+    g.sy = sy; g.sz = sz; g.ntot = ntot;
+    const double *gb = ptr<double>(r_geo);
+    g.dx = gb + geo_off[0]; g.dy = gb + geo_off[1]; g.dz = gb + geo_off[2];
+    g.idx = gb + geo_off[3]; g.idy = gb + geo_off[4]; g.idz = gb + geo_off[5];
+    g.hx = gb + geo_off[6]; g.hy = gb + geo_off[7]; g.hz = gb + geo_off[8];
+    g.ihx = gb + geo_off[9]; g.ihy = gb + geo_off[10]; g.ihz = gb + geo_off[11];
+    g.al[0] = gb + geo_off[12]; g.ah[0] = gb + geo_off[13];
+    g.al[1] = gb + geo_off[14]; g.ah[1] = gb + geo_off[15];
+    g.al[2] = gb + geo_off[16]; g.ah[2] = gb + geo_off[17];
+    g.geo = gb;
+    g.cs = 0;
+    g.mat = ptr<uint8_t>(r_mat);
+    g.flags = ptr<uint8_t>(r_flags);
+    g.mtab = ptr<double>(r_mtab);
+    int pec = 0;
+    for (int f = 0; f < 6; ++f) if (opts.em_bc[f] == ETM_PEC) pec |= 1 << f;
+    g.pec = pec;
+    return g;
+  }
+  DevPorts dev_ports() const {
+    DevPorts p;
+    p.n_edges = int(pe_key.size());
+    p.key = ptr<int64_t>(r_pkey);
+    p.gs = ptr<double>(r_pgs);
+    p.start = ptr<int32_t>(r_pstart);
+    p.wave = ptr<int32_t>(r_pwave);
+    p.wt = ptr<double>(r_pwt);
+    p.J = ptr<double>(r_J);
+    p.n_samples = n_samples;
+    p.er = ptr<double>(r_per);
+    return p;
+  }
+  MechGrid mech_grid() const {
+    MechGrid m;
+    m.g = dev_grid();
+    m.fixed = ptr<uint8_t>(r_fixed);
+    return m;
+  }
+  DevScalars *sc() const { return ptr<DevScalars>(r_sc); }
+  int64_t nidx(int i, int j, int k) const { return int64_t(k) * sz + int64_t(j) * sy + i; }
+};
+
+
+namespace etm {
+EmLaunch em_launch_template(const etm_plan *p);
+etm_status em_one_step(etm_plan *p);
+etm_status thermal_one(etm_plan *p);
+etm_status joule_flush(etm_plan *p);
+etm_status coef_refresh(etm_plan *p);
+etm_status diag_record(etm_plan *p, int old_cur);
+etm_status mech_solve_impl(etm_plan *p);
+}  // namespace etm

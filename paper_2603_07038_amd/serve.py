@@ -1,0 +1,146 @@
+"""Continuous-batching server for design-variant simulations.
+
+Requests (one package design each) arrive over time.  The server keeps a
+batch of bound plans resident on the GPU and advances all of them together
+(one launch per EM step over every admitted variant, chunks replayed from
+HIP graphs).  At every chunk boundary it
+
+  * admits queued requests, first come first served, while a batch slot is
+    free and the summed device footprint stays within the HBM budget;
+  * retires variants whose EM + thermal march is complete: the mechanical
+    solve (Eq. 8 by Jacobi-PCG) and von Mises (Eq. 9) run on the variant's
+    own state, the results are read back, the workspace is released and the
+    request's latency (arrival -> result on the host) is recorded.
+
+A variant's results do not depend on what it shares the GPU with: the
+batched EM step runs the same per-node arithmetic as a solo run.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import List, Optional
+
+import numpy as np
+
+from . import ETM_FIELD_THETA, ETM_FIELD_VM, ETM_PREC_MIXED, Batch, Plan, cfl_dt
+
+
+@dataclasses.dataclass
+class Request:
+    prob: object          # workloads.Problem
+    arrival: float = 0.0  # seconds after the server starts
+    rid: int = 0
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    name: str
+    cells: int
+    em_steps: int
+    arrival: float
+    admitted: float
+    finished: float
+    theta_max: float
+    vm_max: float
+    cg_iters: int
+    cg_relres: float
+    theta: Optional[np.ndarray] = None
+    vm: Optional[np.ndarray] = None
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+class Server:
+    def __init__(self, max_slots: int = 16, hbm_budget: float = 64e9, precision: int = ETM_PREC_MIXED,
+                 chunk: int = 256, keep_fields: bool = False, tune_json: Optional[str] = None):
+        import torch
+        self.torch = torch
+        self.max_slots = max_slots
+        self.hbm_budget = float(hbm_budget)
+        self.precision = precision
+        self.chunk = int(chunk)
+        self.keep_fields = keep_fields
+        self.batch = Batch(max_slots, tune_json)
+        self.stream = torch.cuda.Stream()
+        self.used = 0.0
+        self.active = {}   # slot -> [request, plan, admitted time, EM steps enqueued]
+        self.log: List[str] = []
+
+    def _make_plan(self, req: Request):
+        p = req.prob
+        dt = cfl_dt(p)
+        J = p.sample_J_half(dt, p.n_em_steps)
+        if p.n_em_steps % self.chunk:
+            raise ValueError(f"request {req.rid}: {p.n_em_steps} EM steps is not a multiple of the chunk {self.chunk}")
+        plan = Plan(p, J, dt=dt, precision=self.precision, n_steps=p.n_em_steps, history=False, bind=False)
+        return plan
+
+    def _admit(self, req: Request, plan, now: float) -> bool:
+        if plan.footprint > self.hbm_budget:
+            raise ValueError(f"request {req.rid} needs {plan.footprint} B, above the HBM budget")
+        if len(self.active) >= self.max_slots or self.used + plan.footprint > self.hbm_budget:
+            return False
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            ws = torch.empty(plan.footprint + 256, dtype=torch.uint8, device="cuda")
+            plan.bind(ws, self.stream)
+        slot = self.batch.attach(plan)
+        self.active[slot] = [req, plan, now, 0]
+        self.used += plan.footprint
+        return True
+
+    def _retire(self, slot: int, now_fn) -> Result:
+        req, plan, admitted, _ = self.active.pop(slot)
+        self.batch.detach(slot)
+        plan.mech_solve()
+        info = plan.sync()
+        theta = plan.read(ETM_FIELD_THETA)
+        vm = plan.read(ETM_FIELD_VM)
+        res = Result(rid=req.rid, name=req.prob.name, cells=req.prob.n_cells, em_steps=req.prob.n_em_steps,
+                     arrival=req.arrival, admitted=admitted, finished=now_fn(), theta_max=float(theta.max()),
+                     vm_max=float(vm.max()), cg_iters=int(info["cg_iters"]), cg_relres=float(info["cg_relres"]),
+                     theta=theta if self.keep_fields else None, vm=vm if self.keep_fields else None)
+        self.used -= plan.footprint
+        plan.ws = None
+        del plan
+        return res
+
+    def run(self, requests: List[Request], realtime: bool = True) -> List[Result]:
+        """Serve all requests; arrivals are honoured in wall-clock time when
+        ``realtime`` (else every request is available at once)."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        queue: List = []
+        done: List[Result] = []
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        while pending or queue or self.active:
+            t = now()
+            while pending and (not realtime or pending[0].arrival <= t):
+                r = pending.pop(0)
+                queue.append((r, self._make_plan(r)))
+            while queue:
+                r, plan = queue[0]
+                if not self._admit(r, plan, now()):
+                    break
+                queue.pop(0)
+            if not self.active:
+                if pending and realtime:
+                    time.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
+                continue
+            self.batch.advance(self.chunk, self.stream)
+            for ent in self.active.values():
+                ent[3] += self.chunk
+            for slot in [s for s, ent in self.active.items() if ent[3] >= ent[0].prob.n_em_steps]:
+                done.append(self._retire(slot, now))
+        return done
+
+
+def summarize(results: List[Result], wall: float) -> dict:
+    lat = np.array([r.latency for r in results]) if results else np.zeros(1)
+    return {"requests": len(results), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "designs_per_hour": len(results) / wall * 3600.0 if wall > 0 else None,
+            "cell_steps": int(sum(r.cells * r.em_steps for r in results)), "wall_s": wall}
