@@ -50,6 +50,10 @@ enum {
 enum { ETM_PMC = 0, ETM_PEC = 1 };                          /* EM face condition */
 enum { ETM_MECH_KINEMATIC = 0, ETM_MECH_CLAMP_ZMIN = 1 };   /* mechanical support */
 enum { ETM_PREC_FP64 = 0, ETM_PREC_MIXED = 1 };             /* arithmetic of the path */
+/* Preconditioner of the mechanical CG (Eq. 8): nodal Jacobi, or a geometric
+ * multigrid V-cycle with Galerkin coarse operators (the role the paper's
+ * algebraic multigrid plays, Sec. 4.1). */
+enum { ETM_PRECOND_JACOBI = 0, ETM_PRECOND_MG = 1 };
 
 /* Fields for etm_read / etm_write (always FP64, natural shapes). */
 enum {
@@ -121,6 +125,9 @@ typedef struct {
     const int64_t *probes;
     int64_t history_cap;        /* records kept (0 = enough for n_em_steps_hint) */
     int64_t n_em_steps_hint;    /* expected run length (sizes the history) */
+    int32_t mech_precond;       /* ETM_PRECOND_MG (default) or ETM_PRECOND_JACOBI */
+    int32_t mg_coarse_dofs;     /* multigrid: coarsen until a level has at most this many DOF
+                                   (solved with a dense inverse; default 800, range 3..4000) */
 } etm_opts;
 
 /* What etm_sync reports. */
@@ -135,6 +142,8 @@ typedef struct {
     double ejoule;         /* dissipated EM energy so far [J] */
     int64_t n_records;     /* history records available */
     int64_t cg_iters_total;/* inner CG iterations over all solves */
+    int32_t mg_levels;     /* multigrid levels (0 with Jacobi or before the first solve) */
+    int32_t reserved;
 } etm_run_info;
 
 typedef struct etm_plan etm_plan;

@@ -22,6 +22,7 @@ ETM_OK, ETM_E_INVAL, ETM_E_NOMEM, ETM_E_HIP, ETM_E_UNSTABLE, ETM_E_NOCONV, ETM_E
 ETM_PMC, ETM_PEC = 0, 1
 ETM_MECH_KINEMATIC, ETM_MECH_CLAMP_ZMIN = 0, 1
 ETM_PREC_FP64, ETM_PREC_MIXED = 0, 1
+ETM_PRECOND_JACOBI, ETM_PRECOND_MG = 0, 1
 (ETM_FIELD_EX, ETM_FIELD_EY, ETM_FIELD_EZ, ETM_FIELD_EX_PREV, ETM_FIELD_EY_PREV, ETM_FIELD_EZ_PREV,
  ETM_FIELD_THETA, ETM_FIELD_PSUM, ETM_FIELD_UX, ETM_FIELD_UY, ETM_FIELD_UZ, ETM_FIELD_VM,
  ETM_FIELD_FX, ETM_FIELD_FY, ETM_FIELD_FZ) = range(15)
@@ -56,13 +57,15 @@ class etm_opts(C.Structure):
                 ("em_bc", C.c_int32 * 6), ("em_per_thermal", C.c_int32), ("mech_every_thermal", C.c_int32),
                 ("mech_bc", C.c_int32), ("mech_mask", C.POINTER(C.c_uint8)), ("cg_maxit", C.c_int32),
                 ("cg_rtol", C.c_double), ("history_stride", C.c_int32), ("n_probes", C.c_int32),
-                ("probes", C.POINTER(C.c_int64)), ("history_cap", C.c_int64), ("n_em_steps_hint", C.c_int64)]
+                ("probes", C.POINTER(C.c_int64)), ("history_cap", C.c_int64), ("n_em_steps_hint", C.c_int64),
+                ("mech_precond", C.c_int32), ("mg_coarse_dofs", C.c_int32)]
 
 
 class etm_run_info(C.Structure):
     _fields_ = [("step", C.c_int64), ("status", C.c_int32), ("cg_iters", C.c_int32), ("cg_outer", C.c_int32),
                 ("n_solves", C.c_int32), ("cg_relres", C.c_double), ("theta_max", C.c_double),
-                ("ejoule", C.c_double), ("n_records", C.c_int64), ("cg_iters_total", C.c_int64)]
+                ("ejoule", C.c_double), ("n_records", C.c_int64), ("cg_iters_total", C.c_int64),
+                ("mg_levels", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -204,6 +204,76 @@ hipError_t launch_vec_axpy64(double *y, const float *x, int64_t n, hipStream_t s
 hipError_t launch_von_mises(const MechGrid &M, const double *theta, const double *u[3], double *vm,
                             hipStream_t s);
 
+// One CG iteration's operator half: w = K p, alpha = rz / (p . w) into sc.
+template <typename T>
+hipError_t launch_cg_apply_alpha(const MechGrid &M, const CgVecs<T> &v, double *partials, DevScalars *sc,
+                                 hipStream_t s);
+
+// ---- Geometric multigrid preconditioner (mg.hip) ---------------------------
+// Levels l = 0 (the mesh) .. nlev-1.  Level l+1 keeps every second node of
+// level l along each axis that still has more than one cell (plus the last
+// node when the cell count is odd); prolongation P interpolates linearly in
+// the node coordinates, so it reproduces rigid-body motions on graded grids.
+// Coarse operators are Galerkin products A_{l+1} = P^T A_l P with A_0 = K
+// restricted to the free DOFs, stored as symmetric 27-point 3x3-block
+// stencils; the smoother is Chebyshev on nodal-block-Jacobi, and the
+// coarsest level is solved with a dense inverse.
+constexpr int kMgMaxLevels = 16;
+constexpr int kMgDeg = 2;   // Chebyshev steps before and after the coarse correction
+constexpr int kMgUpper = 14;  // stored stencil blocks: the centre and the 13 offsets after it
+
+template <typename T>
+struct V3 {
+  T *c[3];
+};
+
+struct MgAxis {            // fine-side interpolation table of one axis
+  const int32_t *lo;       // per fine node: lower coarse node of its interval
+  const double *w;         // weight of that node (1 - w on the next one)
+  const int32_t *cpos;     // per coarse node: its fine node
+};
+
+template <typename T>
+struct MgLevel {
+  int nx, ny, nz;          // cells
+  int64_t sy, sz, n;       // node strides; n = entries per component of the level's vectors
+  const T *A;              // [kMgUpper*9][n] stencil blocks (coarse levels; level 0 when it is the coarsest)
+  T *Dinv;                 // [6][n] inverse nodal diagonal block (xx, yy, zz, xy, yz, xz); dead rows zero
+  uint8_t *dead;           // per node: bit c = DOF c outside the space (fixed, or no stiffness)
+  V3<T> xa, xb, d, b;      // smoother iterates, Chebyshev direction, right-hand side (coarse levels)
+  MgAxis ax[3];            // interpolation from level + 1 (unused on the coarsest level)
+  double c1[kMgDeg], c2[kMgDeg];
+};
+
+template <typename T>
+struct MgDev {
+  int nlev;
+  MechGrid M;              // level-0 operator (matrix free)
+  MgLevel<T> L[kMgMaxLevels];
+  T *Ainv;                 // coarsest level: dense inverse over the live DOFs (symmetric, nlive^2)
+  int32_t *live;           // coarsest level: live DOF codes, node * 3 + component
+  int nlive;
+  double *lam;             // [kMgMaxLevels] largest eigenvalue estimates of Dinv A per level
+  double *scale;           // power-iteration normaliser
+};
+
+// Set-up: Galerkin operators of every level, nodal inverses and dead masks.
+template <typename T>
+hipError_t launch_mg_build(const MgDev<T> &G, hipStream_t s);
+// Power iteration for the largest eigenvalue of Dinv A on level l (into G.lam[l]).
+template <typename T>
+hipError_t launch_mg_power(const MgDev<T> &G, int l, int iters, double *partials, hipStream_t s);
+// z = M^{-1} b (one V-cycle); returns where z lives (level-0 xa or xb).
+template <typename T>
+hipError_t launch_mg_vcycle(const MgDev<T> &G, V3<T> b, const DevScalars *sc, V3<T> *z, hipStream_t s);
+// Preconditioned CG with the V-cycle (vectors as for Jacobi CG; z in level-0 buffers).
+template <typename T>
+hipError_t launch_cgmg_setup(const MgDev<T> &G, const CgVecs<T> &v, const T *rhs[3], double *partials,
+                             DevScalars *sc, hipStream_t s);
+template <typename T>
+hipError_t launch_cgmg_iteration(const MgDev<T> &G, const CgVecs<T> &v, double *partials, DevScalars *sc,
+                                 hipStream_t s);
+
 int reduce_blocks(int64_t ntot);
 
 }  // namespace etm

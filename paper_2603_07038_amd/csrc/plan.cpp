@@ -94,6 +94,11 @@ etm_status validate_and_copy(etm_plan *p, const etm_mesh *mesh, const etm_materi
   if (opts->cg_maxit < 1 || !(opts->cg_rtol > 0)) return fail(ETM_E_INVAL, "cg_maxit >= 1 and cg_rtol > 0 required");
   if (opts->history_stride < 0 || opts->n_probes < 0 || (opts->n_probes > 0 && !opts->probes))
     return fail(ETM_E_INVAL, "bad history options");
+  if (opts->mech_precond != ETM_PRECOND_JACOBI && opts->mech_precond != ETM_PRECOND_MG)
+    return fail(ETM_E_INVAL, "bad mech_precond");
+  if (opts->mg_coarse_dofs == 0) p->opts.mg_coarse_dofs = 800;
+  if (p->opts.mg_coarse_dofs < 3 || p->opts.mg_coarse_dofs > 4000)
+    return fail(ETM_E_INVAL, "mg_coarse_dofs must be 0 (default) or 3..4000");
   p->prec = opts->precision;
   p->R = opts->em_per_thermal;
   // time step
@@ -121,6 +126,81 @@ etm_status validate_and_copy(etm_plan *p, const etm_mesh *mesh, const etm_materi
     p->n_samples = 0;
   }
   return ETM_OK;
+}
+
+// Linear interpolation of one axis from its next coarser level: the coarse
+// nodes are every second node (plus the last one when the cell count is
+// odd); fine node i lies in [cpos[lo], cpos[lo+1]] with weight w on lo.
+// An axis of one cell is kept as it is.
+void mg_axis(const std::vector<double> &x, std::vector<int32_t> &lo, std::vector<double> &w,
+             std::vector<int32_t> &cpos, std::vector<double> &xc, bool keep) {
+  const int n = int(x.size()) - 1;
+  cpos.clear();
+  if (keep || n <= 1) {
+    for (int i = 0; i <= n; ++i) cpos.push_back(i);
+  } else {
+    for (int i = 0; i <= n; i += 2) cpos.push_back(i);
+    if (cpos.back() != n) cpos.push_back(n);
+  }
+  lo.assign(n + 1, 0);
+  w.assign(n + 1, 1.0);
+  int I = 0;
+  for (int i = 0; i <= n; ++i) {
+    while (I + 1 < int(cpos.size()) && cpos[I + 1] <= i) ++I;
+    lo[i] = I;
+    w[i] = cpos[I] == i ? 1.0 : (x[cpos[I + 1]] - x[i]) / (x[cpos[I + 1]] - x[cpos[I]]);
+  }
+  xc.resize(cpos.size());
+  for (size_t q = 0; q < cpos.size(); ++q) xc[q] = x[cpos[q]];
+}
+
+// Levels of the mechanical multigrid: coarsen until a level has at most
+// mg_coarse_dofs DOF.  Level 0 uses the plan's padded layout, coarser levels
+// a dense one.
+void mg_levels(etm_plan *p) {
+  p->mg.clear();
+  p->mg_tab.clear();
+  if (p->opts.mech_precond != ETM_PRECOND_MG) return;
+  std::vector<double> xs[3];
+  const std::vector<double> *d[3] = {&p->dx, &p->dy, &p->dz};
+  for (int a = 0; a < 3; ++a) {
+    xs[a].assign(1, 0.0);
+    for (double h : *d[a]) xs[a].push_back(xs[a].back() + h);
+  }
+  MgHostLevel L0;
+  L0.nx = p->nx; L0.ny = p->ny; L0.nz = p->nz;
+  L0.sy = p->sy; L0.sz = p->sz; L0.n = p->ntot;
+  p->mg.push_back(L0);
+  auto put = [&](const void *src, size_t bytes) {
+    const size_t o = align256(p->mg_tab.size());
+    p->mg_tab.resize(o + bytes);
+    std::memcpy(p->mg_tab.data() + o, src, bytes);
+    return o;
+  };
+  std::vector<int32_t> lo, cpos;
+  std::vector<double> w, xc;
+  for (;;) {
+    const MgHostLevel F = p->mg.back();
+    const int64_t dofs = 3 * int64_t(F.nx + 1) * (F.ny + 1) * (F.nz + 1);
+    const bool coarsest = dofs <= p->opts.mg_coarse_dofs || (F.nx <= 1 && F.ny <= 1 && F.nz <= 1) ||
+                          int(p->mg.size()) == kMgMaxLevels;
+    const bool identity = coarsest && p->mg.size() == 1;  // level 0 assembles its own stencil
+    if (coarsest && !identity) break;
+    int cells[3];
+    for (int a = 0; a < 3; ++a) {
+      mg_axis(xs[a], lo, w, cpos, xc, identity);
+      p->mg.back().tab[a][0] = put(lo.data(), lo.size() * 4);
+      p->mg.back().tab[a][1] = put(w.data(), w.size() * 8);
+      p->mg.back().tab[a][2] = put(cpos.data(), cpos.size() * 4);
+      cells[a] = int(cpos.size()) - 1;
+      xs[a] = xc;
+    }
+    if (identity) break;
+    MgHostLevel C;
+    C.nx = cells[0]; C.ny = cells[1]; C.nz = cells[2];
+    C.sy = C.nx + 1; C.sz = C.sy * (C.ny + 1); C.n = C.sz * (C.nz + 1);
+    p->mg.push_back(C);
+  }
 }
 
 etm_status derive(etm_plan *p, const etm_source *src) {
@@ -300,6 +380,7 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   } else {
     p->hist_cap = 0;
   }
+  mg_levels(p);
   // workspace layout
   size_t off = 0;
   auto take = [&](Region &r, size_t bytes) { r.off = off; r.bytes = align256(std::max<size_t>(bytes, 1)); off += r.bytes; };
@@ -344,6 +425,27 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   }
   take(p->r_vm, N * 8);
   take(p->r_stage, N * 8);
+  if (!p->mg.empty()) {
+    const size_t tsz = p->prec == ETM_PREC_FP64 ? 8 : 4;
+    const int nlev = int(p->mg.size());
+    for (int l = 0; l < nlev; ++l) {
+      MgHostLevel &L = p->mg[l];
+      const size_t n = size_t(L.n);
+      if (l > 0 || nlev == 1) take(L.A, size_t(kMgUpper) * 9 * n * tsz);
+      take(L.Dinv, 6 * n * tsz);
+      take(L.dead, n);
+      take(L.xa, 3 * n * tsz);
+      take(L.xb, 3 * n * tsz);
+      take(L.d, 3 * n * tsz);
+      if (l > 0) take(L.b, 3 * n * tsz);
+    }
+    const MgHostLevel &C = p->mg.back();
+    const size_t dofs = 3 * size_t(C.nx + 1) * (C.ny + 1) * (C.nz + 1);
+    take(p->r_mglive, dofs * 4);
+    take(p->r_mgainv, dofs * dofs * tsz);
+    take(p->r_mgtab, p->mg_tab.size());
+    take(p->r_mgsc, (kMgMaxLevels + 2) * 8);
+  }
   p->footprint = off;
   // the march kernel addresses the x, y, z components of a field from one
   // base with a fixed stride: check the layout gives one
@@ -570,6 +672,212 @@ etm_status run_cg(etm_plan *p, const MechGrid &M, const CgVecs<T> &v, const T *r
   return ETM_OK;
 }
 
+template <typename T>
+etm_status run_cgmg(etm_plan *p, const MgDev<T> &G, const CgVecs<T> &v, const T *rhs[3], int budget, int *iters) {
+  etm_status st;
+  HIP_TRY(launch_cgmg_setup<T>(G, v, rhs, p->ptr<double>(p->r_part), p->sc(), p->stream));
+  *iters = 0;
+  const int chunk = 8;
+  for (;;) {
+    if ((st = poll_scalars(p)) != ETM_OK) return st;
+    *iters = p->sc_host->iters;
+    if (p->sc_host->done || *iters >= budget) break;
+    const int n = std::min(chunk, budget - *iters);
+    for (int q = 0; q < n; ++q) HIP_TRY(launch_cgmg_iteration<T>(G, v, p->ptr<double>(p->r_part), p->sc(), p->stream));
+  }
+  return ETM_OK;
+}
+
+template <typename T>
+MgDev<T> mg_dev(const etm_plan *p) {
+  MgDev<T> G{};
+  G.nlev = int(p->mg.size());
+  G.M = p->mech_grid();
+  const char *tb = p->ws + p->r_mgtab.off;
+  for (int l = 0; l < G.nlev; ++l) {
+    const MgHostLevel &H = p->mg[l];
+    MgLevel<T> &L = G.L[l];
+    L.nx = H.nx; L.ny = H.ny; L.nz = H.nz;
+    L.sy = H.sy; L.sz = H.sz; L.n = H.n;
+    L.A = H.A.bytes ? p->ptr<T>(H.A) : nullptr;
+    L.Dinv = p->ptr<T>(H.Dinv);
+    L.dead = p->ptr<uint8_t>(H.dead);
+    auto v3 = [&](const Region &r) {
+      V3<T> v{};
+      if (r.bytes)
+        for (int c = 0; c < 3; ++c) v.c[c] = p->ptr<T>(r) + c * H.n;
+      return v;
+    };
+    L.xa = v3(H.xa); L.xb = v3(H.xb); L.d = v3(H.d); L.b = v3(H.b);
+    for (int a = 0; a < 3; ++a) {
+      L.ax[a].lo = reinterpret_cast<const int32_t *>(tb + H.tab[a][0]);
+      L.ax[a].w = reinterpret_cast<const double *>(tb + H.tab[a][1]);
+      L.ax[a].cpos = reinterpret_cast<const int32_t *>(tb + H.tab[a][2]);
+    }
+    for (int k = 0; k < kMgDeg; ++k) { L.c1[k] = H.c1[k]; L.c2[k] = H.c2[k]; }
+  }
+  G.Ainv = p->ptr<T>(p->r_mgainv);
+  G.live = p->ptr<int32_t>(p->r_mglive);
+  G.nlive = p->mg_nlive;
+  G.lam = p->ptr<double>(p->r_mgsc);
+  G.scale = G.lam + kMgMaxLevels;
+  return G;
+}
+
+// Chebyshev steps for the interval [0.1, 1.1] * lambda_max(Dinv A): the
+// three-term recurrence of Chebyshev acceleration of Richardson iteration,
+// d_0 = r / theta, d_k = c1_k d_{k-1} + c2_k Dinv r_k.
+void cheb_coefs(double lam, double *c1, double *c2) {
+  for (int k = 0; k < kMgDeg; ++k) c1[k] = c2[k] = 0.0;
+  if (!(lam > 0.0) || !std::isfinite(lam)) return;
+  const double hi = 1.1 * lam, lo = 0.1 * lam;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  c2[0] = 1.0 / theta;
+  for (int k = 1; k < kMgDeg; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    c1[k] = rn * rho;
+    c2[k] = 2.0 * rn / delta;
+    rho = rn;
+  }
+}
+
+// Dense inverse of the coarsest operator over its live DOFs (FP64 Cholesky on
+// the host).  A DOF whose pivot vanishes (its coarse basis function adds
+// nothing the others do not span) is dropped and the factorisation redone.
+template <typename T>
+void coarse_inverse(const MgHostLevel &H, const std::vector<T> &A, const std::vector<uint8_t> &dead,
+                    std::vector<int32_t> &live, std::vector<T> &inv) {
+  std::vector<int64_t> cand;
+  for (int k = 0; k <= H.nz; ++k)
+    for (int j = 0; j <= H.ny; ++j)
+      for (int i = 0; i <= H.nx; ++i) {
+        const int64_t n = k * H.sz + j * H.sy + i;
+        for (int c = 0; c < 3; ++c)
+          if (!(dead[n] >> c & 1)) cand.push_back(n * 3 + c);
+      }
+  std::vector<char> drop(cand.size(), 0);
+  const int64_t N = H.n;
+  for (;;) {
+    std::vector<int32_t> col(size_t(3 * N), -1);
+    live.clear();
+    for (size_t q = 0; q < cand.size(); ++q)
+      if (!drop[q]) { col[cand[q]] = int32_t(live.size()); live.push_back(int32_t(cand[q])); }
+    const int m = int(live.size());
+    std::vector<double> D(size_t(m) * m, 0.0);
+    for (int k = 0; k <= H.nz; ++k)
+      for (int j = 0; j <= H.ny; ++j)
+        for (int i = 0; i <= H.nx; ++i) {
+          const int64_t n = k * H.sz + j * H.sy + i;
+          for (int o = 0; o < 27; ++o) {
+            const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+            if (i + ox < 0 || i + ox > H.nx || j + oy < 0 || j + oy > H.ny || k + oz < 0 || k + oz > H.nz) continue;
+            const int64_t nb = n + ox + oy * H.sy + oz * H.sz;
+            double B[9];
+            if (o >= 13) {
+              for (int e = 0; e < 9; ++e) B[e] = double(A[(size_t(o - 13) * 9 + e) * N + n]);
+            } else {
+              for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) B[r * 3 + c] = double(A[(size_t(13 - o) * 9 + c * 3 + r) * N + nb]);
+            }
+            for (int r = 0; r < 3; ++r) {
+              const int rr = col[n * 3 + r];
+              if (rr < 0) continue;
+              for (int c = 0; c < 3; ++c) {
+                const int cc = col[nb * 3 + c];
+                if (cc >= 0) D[size_t(rr) * m + cc] = B[r * 3 + c];
+              }
+            }
+          }
+        }
+    for (int r = 0; r < m; ++r)
+      for (int c = r + 1; c < m; ++c) {
+        const double a = 0.5 * (D[size_t(r) * m + c] + D[size_t(c) * m + r]);
+        D[size_t(r) * m + c] = D[size_t(c) * m + r] = a;
+      }
+    double dmax = 0.0;
+    for (int r = 0; r < m; ++r) dmax = std::max(dmax, D[size_t(r) * m + r]);
+    // Cholesky D = L L^T, row by row (L in the lower triangle of D)
+    int bad = -1;
+    for (int r = 0; r < m && bad < 0; ++r) {
+      double *Lr = &D[size_t(r) * m];
+      for (int c = 0; c <= r; ++c) {
+        const double *Lc = &D[size_t(c) * m];
+        double sum = Lr[c];
+        for (int q = 0; q < c; ++q) sum -= Lr[q] * Lc[q];
+        if (c < r) {
+          Lr[c] = sum / Lc[c];
+        } else if (sum > 1e-13 * dmax) {
+          Lr[r] = std::sqrt(sum);
+        } else {
+          bad = r;
+        }
+      }
+    }
+    if (bad >= 0) {
+      size_t q = 0, seen = 0;
+      for (; q < cand.size(); ++q)
+        if (!drop[q] && int(seen++) == bad) break;
+      drop[q] = 1;
+      continue;
+    }
+    // X = L^{-1}, kept by columns: Xt[c][r] = X[r][c]
+    std::vector<double> Xt(size_t(m) * m, 0.0);
+    for (int c = 0; c < m; ++c) {
+      double *x = &Xt[size_t(c) * m];
+      x[c] = 1.0 / D[size_t(c) * m + c];
+      for (int r = c + 1; r < m; ++r) {
+        const double *Lr = &D[size_t(r) * m];
+        double sum = 0.0;
+        for (int q = c; q < r; ++q) sum += Lr[q] * x[q];
+        x[r] = -sum / Lr[r];
+      }
+    }
+    // D^{-1} = X^T X: entry (r, c) = sum_{q >= max(r,c)} X[q][r] X[q][c]
+    inv.assign(size_t(m) * m, T(0));
+    for (int r = 0; r < m; ++r)
+      for (int c = r; c < m; ++c) {
+        const double *xr = &Xt[size_t(r) * m], *xc = &Xt[size_t(c) * m];
+        double sum = 0.0;
+        for (int q = c; q < m; ++q) sum += xr[q] * xc[q];
+        inv[size_t(r) * m + c] = inv[size_t(c) * m + r] = T(sum);
+      }
+    return;
+  }
+}
+
+constexpr int kMgPowerIters = 12;
+
+template <typename T>
+etm_status mg_setup(etm_plan *p) {
+  MgDev<T> G = mg_dev<T>(p);
+  HIP_TRY(launch_mg_build<T>(G, p->stream));
+  double *part = p->ptr<double>(p->r_part);
+  for (int l = 0; l + 1 < G.nlev; ++l) HIP_TRY(launch_mg_power<T>(G, l, kMgPowerIters, part, p->stream));
+  const MgHostLevel &H = p->mg.back();
+  std::vector<double> lam(kMgMaxLevels, 0.0);
+  std::vector<T> A(size_t(kMgUpper) * 9 * H.n);
+  std::vector<uint8_t> dead(H.n);
+  HIP_TRY(hipMemcpyAsync(lam.data(), G.lam, kMgMaxLevels * 8, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(A.data(), p->ptr<T>(H.A), A.size() * sizeof(T), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(dead.data(), p->ptr<uint8_t>(H.dead), dead.size(), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  std::vector<int32_t> live;
+  std::vector<T> inv;
+  coarse_inverse<T>(H, A, dead, live, inv);
+  if (!live.empty()) {
+    HIP_TRY(hipMemcpyAsync(p->ptr<int32_t>(p->r_mglive), live.data(), live.size() * 4, hipMemcpyHostToDevice,
+                           p->stream));
+    HIP_TRY(hipMemcpyAsync(p->ptr<T>(p->r_mgainv), inv.data(), inv.size() * sizeof(T), hipMemcpyHostToDevice,
+                           p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  p->mg_nlive = int(live.size());
+  for (int l = 0; l + 1 < int(p->mg.size()); ++l) cheb_coefs(lam[l], p->mg[l].c1, p->mg[l].c2);
+  p->mg_ready = true;
+  return ETM_OK;
+}
+
 }  // namespace
 
 etm_status mech_solve_impl(etm_plan *p) {
@@ -580,6 +888,11 @@ etm_status mech_solve_impl(etm_plan *p) {
   for (int c = 0; c < 3; ++c) {
     u64[c] = p->ptr<double>(p->r_u64[c]); f64[c] = p->ptr<double>(p->r_f64[c]);
     r64[c] = p->ptr<double>(p->r_r64[c]); dinv64[c] = p->ptr<double>(p->r_dinv64[c]);
+  }
+  const bool use_mg = !p->mg.empty();
+  if (use_mg && !p->mg_ready) {
+    st = p->prec == ETM_PREC_FP64 ? mg_setup<double>(p) : mg_setup<float>(p);
+    if (st != ETM_OK) return st;
   }
   if (!p->dinv_ready) {
     HIP_TRY(launch_mech_diag(M, dinv64, p->stream));
@@ -609,7 +922,9 @@ etm_status mech_solve_impl(etm_plan *p) {
     while (total < maxit) {
       if ((st = set_tol2(p, target2)) != ETM_OK) return st;
       int it = 0;
-      if ((st = run_cg<double>(p, M, v, cf64, 0, maxit - total, &it)) != ETM_OK) return st;
+      st = use_mg ? run_cgmg<double>(p, mg_dev<double>(p), v, cf64, maxit - total, &it)
+                  : run_cg<double>(p, M, v, cf64, 0, maxit - total, &it);
+      if (st != ETM_OK) return st;
       total += it;
       // true residual
       HIP_TRY(launch_residual64(M, cf64, cu64, r64, p->ptr<double>(p->r_part), p->sc(), p->stream));
@@ -642,7 +957,9 @@ etm_status mech_solve_impl(etm_plan *p) {
       }
       if ((st = set_tol2(p, std::max(inner_rtol * inner_rtol * rr, 0.25 * target2))) != ETM_OK) return st;
       int it = 0;
-      if ((st = run_cg<float>(p, M, v, rhs32, 1, maxit - total, &it)) != ETM_OK) return st;
+      st = use_mg ? run_cgmg<float>(p, mg_dev<float>(p), v, rhs32, maxit - total, &it)
+                  : run_cg<float>(p, M, v, rhs32, 1, maxit - total, &it);
+      if (st != ETM_OK) return st;
       total += it;
       for (int c = 0; c < 3; ++c) HIP_TRY(launch_vec_axpy64(u64[c], v.u[c], N, p->stream));
       if (it == 0) break;
@@ -678,6 +995,8 @@ etm_status etm_opts_default(etm_opts *o) {
   o->mech_bc = ETM_MECH_KINEMATIC;
   o->cg_maxit = 200000;
   o->cg_rtol = 1e-8;
+  o->mech_precond = ETM_PRECOND_MG;
+  o->mg_coarse_dofs = 800;
   return ETM_OK;
 }
 
@@ -759,7 +1078,8 @@ etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
       (st = up(p->r_pwave, p->pw_wave.data(), p->pw_wave.size() * 4)) ||
       (st = up(p->r_pwt, p->pw_wt.data(), p->pw_wt.size() * 8)) ||
       (st = up(p->r_J, p->J.data(), p->J.size() * 8)) ||
-      (st = up(p->r_probes, p->probes_dev.data(), p->probes_dev.size() * 8)))
+      (st = up(p->r_probes, p->probes_dev.data(), p->probes_dev.size() * 8)) ||
+      (st = up(p->r_mgtab, p->mg_tab.data(), p->mg_tab.size())))
     return st;
   p->bound = true;
   if ((st = coef_refresh(p)) != ETM_OK) return st;
@@ -768,6 +1088,7 @@ etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
   p->n_solves = 0; p->cg_iters = 0; p->cg_outer = 0; p->cg_total = 0; p->cg_relres = 0;
   p->host_status = ETM_OK;
   p->dinv_ready = false;
+  p->mg_ready = false;
   p->joule_pending = false;
   return ETM_OK;
 }
@@ -816,6 +1137,8 @@ etm_status etm_sync(etm_plan *p, etm_run_info *info) {
     info->ejoule = s.ejoule;
     info->n_records = p->rec;
     info->cg_iters_total = p->cg_total;
+    info->mg_levels = p->mg_ready ? int32_t(p->mg.size()) : 0;
+    info->reserved = 0;
   }
   if (s.status != ETM_OK) return fail(s.status, "non-finite field detected on the device");
   if (p->host_status != ETM_OK) return fail(p->host_status, "mechanical solve did not converge");

@@ -25,6 +25,15 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 using namespace etm;
 
+// One level of the mechanical multigrid hierarchy (host view).
+struct MgHostLevel {
+  int nx = 0, ny = 0, nz = 0;          // cells
+  int64_t sy = 0, sz = 0, n = 0;       // node strides, entries per vector component
+  Region A, Dinv, dead, xa, xb, d, b;  // device regions (A: coarse levels only)
+  size_t tab[3][3] = {};               // offsets in r_mgtab of lo, w, cpos per axis (from level + 1)
+  double c1[kMgDeg] = {}, c2[kMgDeg] = {};
+};
+
 struct etm_plan {
   // ---- inputs (deep copies)
   int nx = 0, ny = 0, nz = 0, n_mat = 0;
@@ -61,6 +70,12 @@ struct etm_plan {
   Region r_u64[3], r_f64[3], r_r64[3], r_p64[3], r_w64[3], r_dinv64[3];
   Region r_u32[3], r_r32[3], r_p32[3], r_w32[3], r_dinv32[3], r_rhs32[3];
   Region r_vm, r_stage;
+  // multigrid preconditioner of the mechanical CG
+  std::vector<MgHostLevel> mg;         // empty with the Jacobi preconditioner
+  std::vector<char> mg_tab;            // interpolation tables (uploaded at bind)
+  Region r_mgtab, r_mglive, r_mgainv, r_mgsc;
+  int mg_nlive = 0;
+  bool mg_ready = false;
   size_t footprint = 0;
   // ---- bound state
   char *ws = nullptr;

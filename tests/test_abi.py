@@ -64,7 +64,8 @@ def test_auto_dt_matches_oracle_cfl(maker):
 
 
 def test_footprint_fits_full_scale_package():
-    """The 1024x1024x128 package's FP64 plan fits one MI355X's 288 GB with room."""
+    """The 1024x1024x128 package's plan (state, CG vectors and the multigrid
+    hierarchy) fits one MI355X's 288 GB with room."""
     nx, ny, nz = 1024, 1024, 128
     p = W.Problem(name="big", dx=np.full(nx, 1e-6), dy=np.full(ny, 1e-6), dz=np.full(nz, 1e-6),
                   mat=np.ones((nz, ny, nx), dtype=np.uint8), props=W.package_materials(), waves=[],
@@ -74,7 +75,7 @@ def test_footprint_fits_full_scale_package():
         assert st == 0
         fp = C.c_size_t()
         etm.load().etm_plan_footprint(h, C.byref(fp))
-        assert fp.value < 64e9
+        assert fp.value < (128e9 if prec == etm.ETM_PREC_FP64 else 80e9)
         etm.load().etm_plan_destroy(h)
 
 
@@ -106,6 +107,10 @@ def test_validation_errors():
     # bad options
     assert _create(p, J, em_per_thermal=0)[0] == etm.ETM_E_INVAL
     assert _create(p, J, precision=7)[0] == etm.ETM_E_INVAL
+    assert _create(p, J, mech_precond=5)[0] == etm.ETM_E_INVAL
+    assert _create(p, J, mg_coarse_dofs=2)[0] == etm.ETM_E_INVAL
+    assert _create(p, J, mg_coarse_dofs=5000)[0] == etm.ETM_E_INVAL
+    assert _create(p, J, mech_precond=etm.ETM_PRECOND_JACOBI)[0] == etm.ETM_OK
 
 
 def test_calls_before_bind_are_state_errors():
