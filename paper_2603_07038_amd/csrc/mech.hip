@@ -113,30 +113,20 @@ __global__ __launch_bounds__(256) void rhs_finalize(const double *part, int64_t 
 }
 
 // ---- CG -----------------------------------------------------------------------
+// Jacobi-CG start: r = b - K u, z = Dinv r, p = z; partial r.z and r.r.
 template <typename T>
-__global__ __launch_bounds__(256) void cg_setup_kernel(MechGrid M, CgVecs<T> v, const T *r0, const T *r1,
-                                                       const T *r2, int zero_init, double *partials) {
-  const DevGrid &g = M.g;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  double rz = 0.0, rr = 0.0;
-  if (i <= g.nx && j <= g.ny) {
-    const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
-    T yx = T(0), yy = T(0), yz = T(0);
-    if (!zero_init) {
-      const T *pv[3] = {v.u[0], v.u[1], v.u[2]};
-      node_apply<T>(M, i, j, k, n, pv, yx, yy, yz);
-    }
-    const T rx = r0[n] - yx, ry = r1[n] - yy, rzv = r2[n] - yz;
-    const T zx = v.dinv[0][n] * rx, zy = v.dinv[1][n] * ry, zz = v.dinv[2][n] * rzv;
-    v.r[0][n] = rx; v.r[1][n] = ry; v.r[2][n] = rzv;
+struct EpiJacobiStart {
+  CgVecs<T> v;
+  const T *b0, *b1, *b2;
+  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T *, double *red) const {
+    const T rx = b0[n] - y[0], ry = b1[n] - y[1], rz = b2[n] - y[2];
+    const T zx = v.dinv[0][n] * rx, zy = v.dinv[1][n] * ry, zz = v.dinv[2][n] * rz;
+    v.r[0][n] = rx; v.r[1][n] = ry; v.r[2][n] = rz;
     v.p[0][n] = zx; v.p[1][n] = zy; v.p[2][n] = zz;
-    rz = double(rx) * double(zx) + double(ry) * double(zy) + double(rzv) * double(zz);
-    rr = double(rx) * double(rx) + double(ry) * double(ry) + double(rzv) * double(rzv);
+    red[0] += double(rx) * double(zx) + double(ry) * double(zy) + double(rz) * double(zz);
+    red[1] += double(rx) * double(rx) + double(ry) * double(ry) + double(rz) * double(rz);
   }
-  const double s[2] = {rz, rr};
-  const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  block_sums<2>(s, partials + b * kRedWidth);
-}
+};
 
 __global__ __launch_bounds__(256) void cg_setup_finalize(const double *part, int64_t nb, DevScalars *sc) {
   __shared__ double out[2];
@@ -150,25 +140,15 @@ __global__ __launch_bounds__(256) void cg_setup_finalize(const double *part, int
   }
 }
 
+// w = K p; partial p.w.
 template <typename T>
-__global__ __launch_bounds__(256) void cg_apply_kernel(MechGrid M, CgVecs<T> v, const DevScalars *sc,
-                                                       double *partials) {
-  if (sc->done) return;
-  const DevGrid &g = M.g;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  double pw = 0.0;
-  if (i <= g.nx && j <= g.ny) {
-    const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
-    const T *pv[3] = {v.p[0], v.p[1], v.p[2]};
-    T yx, yy, yz;
-    node_apply<T>(M, i, j, k, n, pv, yx, yy, yz);
-    v.w[0][n] = yx; v.w[1][n] = yy; v.w[2][n] = yz;
-    pw = double(v.p[0][n]) * double(yx) + double(v.p[1][n]) * double(yy) + double(v.p[2][n]) * double(yz);
+struct EpiApplyDot {
+  T *w0, *w1, *w2;
+  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T xc[3], double *red) const {
+    w0[n] = y[0]; w1[n] = y[1]; w2[n] = y[2];
+    red[0] += double(xc[0]) * double(y[0]) + double(xc[1]) * double(y[1]) + double(xc[2]) * double(y[2]);
   }
-  const double s[1] = {pw};
-  const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  block_sums<1>(s, partials + b * kRedWidth);
-}
+};
 
 __global__ __launch_bounds__(256) void cg_alpha_finalize(const double *part, int64_t nb, DevScalars *sc) {
   if (sc->done) return;
@@ -229,26 +209,16 @@ __global__ __launch_bounds__(256) void cg_p_kernel(CgVecs<T> v, int64_t ntot, co
   }
 }
 
-__global__ __launch_bounds__(256) void residual64_kernel(MechGrid M, const double *f0, const double *f1,
-                                                         const double *f2, const double *u0, const double *u1,
-                                                         const double *u2, double *r0, double *r1, double *r2,
-                                                         double *partials) {
-  const DevGrid &g = M.g;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  double rr = 0.0;
-  if (i <= g.nx && j <= g.ny) {
-    const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
-    const double *pv[3] = {u0, u1, u2};
-    double yx, yy, yz;
-    node_apply<double>(M, i, j, k, n, pv, yx, yy, yz);
-    const double rx = f0[n] - yx, ry = f1[n] - yy, rzv = f2[n] - yz;
-    r0[n] = rx; r1[n] = ry; r2[n] = rzv;
-    rr = rx * rx + ry * ry + rzv * rzv;
+// r64 = f - K u64; partial |r|^2.
+struct EpiResidual64 {
+  const double *f0, *f1, *f2;
+  double *r0, *r1, *r2;
+  __device__ void operator()(int, int, int, int64_t n, const double y[3], const double *, double *red) const {
+    const double rx = f0[n] - y[0], ry = f1[n] - y[1], rz = f2[n] - y[2];
+    r0[n] = rx; r1[n] = ry; r2[n] = rz;
+    red[0] += rx * rx + ry * ry + rz * rz;
   }
-  const double s[1] = {rr};
-  const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  block_sums<1>(s, partials + b * kRedWidth);
-}
+};
 
 __global__ __launch_bounds__(256) void residual_finalize(const double *part, int64_t nb, DevScalars *sc) {
   __shared__ double out[1];
@@ -260,6 +230,20 @@ __global__ void cast_kernel(const void *src, int src_f32, void *dst, int dst_f32
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
     const double x = src_f32 ? double(((const float *)src)[t]) : ((const double *)src)[t];
     if (dst_f32) ((float *)dst)[t] = float(x); else ((double *)dst)[t] = x;
+  }
+}
+
+// u <- u + s (u - u_prev), u_prev <- old u (per component arrays).
+__global__ void extrapolate_kernel(double *u0, double *u1, double *u2, double *v0, double *v1, double *v2, double sc,
+                                   int64_t n) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
+    double *u[3] = {u0, u1, u2}, *v[3] = {v0, v1, v2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double a = u[c][t], b = v[c][t];
+      u[c][t] = a + sc * (a - b);
+      v[c][t] = a;
+    }
   }
 }
 
@@ -323,20 +307,19 @@ hipError_t launch_mech_rhs(const MechGrid &M, const double *theta, double *f[3],
 template <typename T>
 hipError_t launch_cg_setup(const MechGrid &M, const CgVecs<T> &v, const T *rhs[3], double *partials,
                            DevScalars *sc, hipStream_t s) {
-  const dim3 grid = node_grid(M.g);
-  hipLaunchKernelGGL((cg_setup_kernel<T>), grid, dim3(BX, BY), 0, s, M, v, rhs[0], rhs[1], rhs[2], 0, partials);
+  const T *x[3] = {v.u[0], v.u[1], v.u[2]};
+  hipError_t e = launch_hex8<T, 2>(M, x, EpiJacobiStart<T>{v, rhs[0], rhs[1], rhs[2]}, partials, nullptr, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cg_setup_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
-                     int64_t(grid.x) * grid.y * grid.z, sc);
+                     cell_blocks(M.g, cell_kchunk(M.g)), sc);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cg_iteration(const MechGrid &M, const CgVecs<T> &v, double *partials, DevScalars *sc,
                                hipStream_t s) {
-  const dim3 grid = node_grid(M.g);
-  const int64_t nb = int64_t(grid.x) * grid.y * grid.z;
-  hipLaunchKernelGGL((cg_apply_kernel<T>), grid, dim3(BX, BY), 0, s, M, v, (const DevScalars *)sc, partials);
-  hipLaunchKernelGGL(cg_alpha_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc);
+  hipError_t e = launch_cg_apply_alpha<T>(M, v, partials, sc, s);
+  if (e != hipSuccess) return e;
   const int fb = flat_blocks(M.g.ntot);
   hipLaunchKernelGGL((cg_update_kernel<T>), dim3(fb), dim3(256), 0, s, v, M.g.ntot, (const DevScalars *)sc, partials);
   hipLaunchKernelGGL(cg_beta_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, int64_t(fb), sc);
@@ -347,10 +330,11 @@ hipError_t launch_cg_iteration(const MechGrid &M, const CgVecs<T> &v, double *pa
 template <typename T>
 hipError_t launch_cg_apply_alpha(const MechGrid &M, const CgVecs<T> &v, double *partials, DevScalars *sc,
                                  hipStream_t s) {
-  const dim3 grid = node_grid(M.g);
-  const int64_t nb = int64_t(grid.x) * grid.y * grid.z;
-  hipLaunchKernelGGL((cg_apply_kernel<T>), grid, dim3(BX, BY), 0, s, M, v, (const DevScalars *)sc, partials);
-  hipLaunchKernelGGL(cg_alpha_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc);
+  const T *x[3] = {v.p[0], v.p[1], v.p[2]};
+  hipError_t e = launch_hex8<T, 1>(M, x, EpiApplyDot<T>{v.w[0], v.w[1], v.w[2]}, partials, sc, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cg_alpha_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
+                     cell_blocks(M.g, cell_kchunk(M.g)), sc);
   return hipGetLastError();
 }
 
@@ -369,16 +353,22 @@ template hipError_t launch_cg_iteration<float>(const MechGrid &, const CgVecs<fl
 
 hipError_t launch_residual64(const MechGrid &M, const double *f[3], const double *u[3], double *r[3],
                              double *partials, DevScalars *sc, hipStream_t s) {
-  const dim3 grid = node_grid(M.g);
-  hipLaunchKernelGGL(residual64_kernel, grid, dim3(BX, BY), 0, s, M, f[0], f[1], f[2], u[0], u[1], u[2], r[0], r[1],
-                     r[2], partials);
+  hipError_t e =
+      launch_hex8<double, 1>(M, u, EpiResidual64{f[0], f[1], f[2], r[0], r[1], r[2]}, partials, nullptr, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(residual_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
-                     int64_t(grid.x) * grid.y * grid.z, sc);
+                     cell_blocks(M.g, cell_kchunk(M.g)), sc);
   return hipGetLastError();
 }
 
 hipError_t launch_vec_cast(const void *src, int src_f32, void *dst, int dst_f32, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(cast_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, src, src_f32, dst, dst_f32, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_extrapolate(double *u[3], double *uprev[3], double sc, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(extrapolate_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, u[0], u[1], u[2], uprev[0], uprev[1],
+                     uprev[2], sc, n);
   return hipGetLastError();
 }
 

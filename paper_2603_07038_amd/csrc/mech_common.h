@@ -1,8 +1,11 @@
 // Device helpers shared by the mechanics kernels (mech.hip) and the
 // multigrid preconditioner (mg.hip): node-grid launch shape, wave64 and block
-// reductions in FP64, and the matrix-free HEX8 stiffness of Eq. (8).
+// reductions in FP64, and the matrix-free HEX8 stiffness of Eq. (8) applied
+// cell by cell.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "etm_internal.h"
 
@@ -55,57 +58,220 @@ __device__ __forceinline__ void sum_partials(const double *part, int64_t nb, dou
   block_sums<NS>(v, out);
 }
 
-// K_e rows of local node a applied to the cell's nodal vectors, accumulated
-// into y.  pv[3] point at the node-shaped input arrays; nb0 is the index of
-// the cell's low corner node.
+// ---- cell-based HEX8 apply ---------------------------------------------------
+// For a box cell the element stiffness is a sum of Kronecker products of 1D
+// 2x2 factors: mass m(a,b) = int phi_a phi_b, stiffness k = int phi_a' phi_b',
+// and the mixed g = int phi_a' phi_b, g^T.  In the per-axis basis
+// (sum, difference) = (v0 + v1, v1 - v0) each factor is diagonal or a swap:
+//   m: diag(h/2, h/6)   k: diag(0, 2/h)   g: sum -> difference   g^T: difference -> sum
+// so K_e u = H^-1 D H u with H the tensor sum/difference transform, and D
+// has 24 diagonal entries and 24 single-entry couplings between components.
+
+// Forward transform of 8 corner values (index ax + 2 ay + 4 az) in place.
 template <typename T>
-__device__ __forceinline__ void cell_rows(const DevGrid &g, int ci, int cj, int ck, int ax, int ay, int az,
-                                          int64_t nb0, const T *const *pv, T &yx, T &yy, T &yz) {
-  const double *row = g.mtab + g.mat[nb0] * kMatStride;
-  if (row[MC_VOID] != 0.0) return;
-  const T lam = T(row[MC_LAMBDA]), mu = T(row[MC_MU]);
-  const T hx = T(g.dx[ci]), hy = T(g.dy[cj]), hz = T(g.dz[ck]);
-  const T ihx = T(g.idx[ci]), ihy = T(g.idy[cj]), ihz = T(g.idz[ck]);
-  const T gax = ax ? T(0.5) : T(-0.5), gay = ay ? T(0.5) : T(-0.5), gaz = az ? T(0.5) : T(-0.5);
+__device__ __forceinline__ void haar3(T v[8]) {
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
-    const int64_t nb = nb0 + bx + by * g.sy + bz * g.sz;
-    const T px = pv[0][nb], py = pv[1][nb], pz = pv[2][nb];
-    const bool sx = ax == bx, sy = ay == by, sz = az == bz;
-    const T mx = hx * (sx ? T(1.0 / 3.0) : T(1.0 / 6.0)), my = hy * (sy ? T(1.0 / 3.0) : T(1.0 / 6.0)),
-            mz = hz * (sz ? T(1.0 / 3.0) : T(1.0 / 6.0));
-    const T kx = sx ? ihx : -ihx, ky = sy ? ihy : -ihy, kz = sz ? ihz : -ihz;
-    const T gbx = bx ? T(0.5) : T(-0.5), gby = by ? T(0.5) : T(-0.5), gbz = bz ? T(0.5) : T(-0.5);
-    const T Axx = kx * my * mz, Ayy = mx * ky * mz, Azz = mx * my * kz;
-    const T Lp = mu * (Axx + Ayy + Azz);
-    const T Axy = gax * gby * mz, Ayx = gay * gbx * mz;
-    const T Axz = gax * my * gbz, Azx = gaz * my * gbx;
-    const T Ayz = mx * gay * gbz, Azy = mx * gaz * gby;
-    yx += ((lam + mu) * Axx + Lp) * px + (lam * Axy + mu * Ayx) * py + (lam * Axz + mu * Azx) * pz;
-    yy += (lam * Ayx + mu * Axy) * px + ((lam + mu) * Ayy + Lp) * py + (lam * Ayz + mu * Azy) * pz;
-    yz += (lam * Azx + mu * Axz) * px + (lam * Azy + mu * Ayz) * py + ((lam + mu) * Azz + Lp) * pz;
+  for (int a = 0; a < 8; a += 2) { const T s = v[a] + v[a + 1], d = v[a + 1] - v[a]; v[a] = s; v[a + 1] = d; }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int a = (q & 1) | ((q & 2) << 1);
+    const T s = v[a] + v[a + 2], d = v[a + 2] - v[a]; v[a] = s; v[a + 2] = d;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) { const T s = v[a] + v[a + 4], d = v[a + 4] - v[a]; v[a] = s; v[a + 4] = d; }
+}
+
+// Inverse transform without its factor 1/8 (folded into the operator).
+template <typename T>
+__device__ __forceinline__ void ihaar3(T v[8]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) { const T s = v[a], d = v[a + 4]; v[a] = s - d; v[a + 4] = s + d; }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int a = (q & 1) | ((q & 2) << 1);
+    const T s = v[a], d = v[a + 2]; v[a] = s - d; v[a + 2] = s + d;
+  }
+#pragma unroll
+  for (int a = 0; a < 8; a += 2) { const T s = v[a], d = v[a + 1]; v[a] = s - d; v[a + 1] = s + d; }
+}
+
+// (ux, uy, uz) <- K_e (ux, uy, uz) for a box cell of widths h and Lame
+// constants lam, mu (corner index ax + 2 ay + 4 az).
+template <typename T>
+__device__ __forceinline__ void hex8_cell(T ux[8], T uy[8], T uz[8], T hx, T hy, T hz, T lam, T mu) {
+  haar3(ux); haar3(uy); haar3(uz);
+  const T mx[2] = {hx * T(0.5), hx * T(1.0 / 6.0)}, my[2] = {hy * T(0.5), hy * T(1.0 / 6.0)},
+          mz[2] = {hz * T(0.5), hz * T(1.0 / 6.0)};
+  const T kx = T(2) / hx, ky = T(2) / hy, kz = T(2) / hz;
+  const T el = T(0.125) * lam, em = T(0.125) * mu;
+  T vx[8], vy[8], vz[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
+    const T t1 = px ? kx * my[py] * mz[pz] : T(0);
+    const T t2 = py ? mx[px] * ky * mz[pz] : T(0);
+    const T t3 = pz ? mx[px] * my[py] * kz : T(0);
+    const T s = t1 + t2 + t3;
+    vx[p] = (el * t1 + em * (s + t1)) * ux[p];
+    vy[p] = (el * t2 + em * (s + t2)) * uy[p];
+    vz[p] = (el * t3 + em * (s + t3)) * uz[p];
+  }
+#pragma unroll
+  for (int pz = 0; pz < 2; ++pz) {  // x-y coupling: (sum x, diff y) <-> (diff x, sum y)
+    const int ai = 2 + 4 * pz, ao = 1 + 4 * pz;
+    const T l = el * mz[pz], m = em * mz[pz];
+    vx[ao] += l * uy[ai]; vx[ai] += m * uy[ao];
+    vy[ai] += l * ux[ao]; vy[ao] += m * ux[ai];
+  }
+#pragma unroll
+  for (int py = 0; py < 2; ++py) {  // x-z coupling
+    const int ai = 2 * py + 4, ao = 1 + 2 * py;
+    const T l = el * my[py], m = em * my[py];
+    vx[ao] += l * uz[ai]; vx[ai] += m * uz[ao];
+    vz[ai] += l * ux[ao]; vz[ao] += m * ux[ai];
+  }
+#pragma unroll
+  for (int px = 0; px < 2; ++px) {  // y-z coupling
+    const int ai = px + 4, ao = px + 2;
+    const T l = el * mx[px], m = em * mx[px];
+    vy[ao] += l * uz[ai]; vy[ai] += m * uz[ao];
+    vz[ai] += l * uy[ao]; vz[ao] += m * uy[ai];
+  }
+  ihaar3(vx); ihaar3(vy); ihaar3(vz);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) { ux[a] = vx[a]; uy[a] = vy[a]; uz[a] = vz[a]; }
+}
+
+// y = K x over the mesh, cell by cell, with an epilogue per node.
+// A block of CX x CY threads owns a tile of CX x CY cells and the
+// (CX-1) x (CY-1) nodes whose four in-plane cells all lie in the tile, and
+// marches up z over kchunk node planes: for each cell layer it stages the
+// next node plane of x in LDS (three-plane ring), every thread applies its
+// cell's K_e and stores the 24 results in LDS, and each owned node adds the
+// corners of its four cells in a fixed order, so y is deterministic.
+// Fixed DOFs give zero rows; x is taken as zero on them.  The epilogue sees
+// (i, j, k, n, y, x at the node, per-thread partial sums).
+constexpr int CX = 32, CY = 8;
+
+inline dim3 cell_grid(const DevGrid &g, int kchunk) {
+  return dim3((g.nx + 1 + CX - 2) / (CX - 1), (g.ny + 1 + CY - 2) / (CY - 1), (g.nz + 1 + kchunk - 1) / kchunk);
+}
+inline int cell_kchunk(const DevGrid &g) {
+  const int64_t tiles = int64_t((g.nx + 1 + CX - 2) / (CX - 1)) * ((g.ny + 1 + CY - 2) / (CY - 1));
+  const int64_t want = std::max<int64_t>(1, (tiles * (g.nz + 1)) / 4096);
+  return int(std::max<int64_t>(4, std::min<int64_t>(32, want)));
+}
+
+template <typename T, int NS, class Epi>
+__global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T *x0, const T *x1, const T *x2,
+                                                             int kchunk, Epi epi, double *partials,
+                                                             const DevScalars *sc) {
+  if (sc && sc->done) return;
+  const DevGrid &g = M.g;
+  __shared__ T xs[3][3][CY + 1][CX + 1];
+  __shared__ T co[24][CY][CX];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * CX + tx;
+  const int i0 = blockIdx.x * (CX - 1), j0 = blockIdx.y * (CY - 1);
+  const int k0 = blockIdx.z * kchunk, k1 = min(k0 + kchunk, g.nz + 1);
+  const int ci = i0 - 1 + tx, cj = j0 - 1 + ty;
+  const bool cin = ci >= 0 && ci < g.nx && cj >= 0 && cj < g.ny;
+  const int ni = i0 + tx, nj = j0 + ty;
+  const bool own = tx < CX - 1 && ty < CY - 1 && ni <= g.nx && nj <= g.ny;
+  const T hx = cin ? T(g.dx[ci]) : T(1), hy = cin ? T(g.dy[cj]) : T(1);
+  const T *xv[3] = {x0, x1, x2};
+  double red[NS > 0 ? NS : 1];
+#pragma unroll
+  for (int q = 0; q < (NS > 0 ? NS : 1); ++q) red[q] = 0.0;
+  auto load_plane = [&](int k) {
+    T(*dst)[CY + 1][CX + 1] = xs[(k + 3) % 3];
+    for (int t = tid; t < (CY + 1) * (CX + 1); t += CX * CY) {
+      const int r = t / (CX + 1), c = t - r * (CX + 1);
+      const int i = i0 - 1 + c, j = j0 - 1 + r;
+      const bool ok = k >= 0 && k <= g.nz && i >= 0 && i <= g.nx && j >= 0 && j <= g.ny;
+      const int64_t n = ok ? int64_t(k) * g.sz + int64_t(j) * g.sy + i : 0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) dst[q][r][c] = ok ? xv[q][n] : T(0);
+    }
+  };
+  T acc[3] = {T(0), T(0), T(0)};
+  load_plane(k0 - 1);
+  for (int ck = k0 - 1; ck < k1; ++ck) {
+    load_plane(ck + 1);
+    __syncthreads();
+    T ux[8], uy[8], uz[8];
+    bool live = cin && ck >= 0 && ck < g.nz;
+    T lam = T(0), mu = T(0), hz = T(1);
+    if (live) {
+      const double *row = g.mtab + g.mat[int64_t(ck) * g.sz + int64_t(cj) * g.sy + ci] * kMatStride;
+      live = row[MC_VOID] == 0.0;
+      lam = T(row[MC_LAMBDA]);
+      mu = T(row[MC_MU]);
+      hz = T(g.dz[ck]);
+    }
+    if (live) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+        const T(*pl)[CY + 1][CX + 1] = xs[(ck + az + 3) % 3];
+        ux[a] = pl[0][ty + ay][tx + ax];
+        uy[a] = pl[1][ty + ay][tx + ax];
+        uz[a] = pl[2][ty + ay][tx + ax];
+      }
+      hex8_cell<T>(ux, uy, uz, hx, hy, hz, lam, mu);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) ux[a] = uy[a] = uz[a] = T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      co[a * 3 + 0][ty][tx] = ux[a];
+      co[a * 3 + 1][ty][tx] = uy[a];
+      co[a * 3 + 2][ty][tx] = uz[a];
+    }
+    __syncthreads();
+    if (own) {
+      // node (ni, nj) is corner (1,1) of cell (tx,ty), (0,1) of (tx+1,ty),
+      // (1,0) of (tx,ty+1) and (0,0) of (tx+1,ty+1)
+      T y[3], top[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        y[q] = acc[q] + co[3 * 3 + q][ty][tx] + co[2 * 3 + q][ty][tx + 1] + co[1 * 3 + q][ty + 1][tx] +
+               co[0 * 3 + q][ty + 1][tx + 1];
+        top[q] = co[7 * 3 + q][ty][tx] + co[6 * 3 + q][ty][tx + 1] + co[5 * 3 + q][ty + 1][tx] +
+                 co[4 * 3 + q][ty + 1][tx + 1];
+      }
+      if (ck >= k0) {
+        const int64_t n = int64_t(ck) * g.sz + int64_t(nj) * g.sy + ni;
+        const uint8_t f = M.fixed[n];
+        if (f & 1) y[0] = T(0);
+        if (f & 2) y[1] = T(0);
+        if (f & 4) y[2] = T(0);
+        const T(*pl)[CY + 1][CX + 1] = xs[(ck + 3) % 3];
+        const T xc[3] = {pl[0][ty + 1][tx + 1], pl[1][ty + 1][tx + 1], pl[2][ty + 1][tx + 1]};
+        epi(ni, nj, ck, n, y, xc, red);
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[q] = top[q];
+    }
+  }
+  if constexpr (NS > 0) {
+    const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_sums<NS>(red, partials + b * kRedWidth);
   }
 }
 
-// y = K p at node (i,j,k) = index n (free rows only).
-template <typename T>
-__device__ __forceinline__ void node_apply(const MechGrid &M, int i, int j, int k, int64_t n, const T *const *pv,
-                                           T &yx, T &yy, T &yz) {
-  const DevGrid &g = M.g;
-  yx = yy = yz = T(0);
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-    const int ci = i - 1 + ox, cj = j - 1 + oy, ck = k - 1 + oz;
-    if (ci < 0 || ci >= g.nx || cj < 0 || cj >= g.ny || ck < 0 || ck >= g.nz) continue;
-    const int64_t nb0 = n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz;
-    cell_rows<T>(g, ci, cj, ck, 1 - ox, 1 - oy, 1 - oz, nb0, pv, yx, yy, yz);
-  }
-  const uint8_t f = M.fixed[n];
-  if (f & 1) yx = T(0);
-  if (f & 2) yy = T(0);
-  if (f & 4) yz = T(0);
+inline int64_t cell_blocks(const DevGrid &g, int kchunk) {
+  const dim3 d = cell_grid(g, kchunk);
+  return int64_t(d.x) * d.y * d.z;
+}
+
+template <typename T, int NS, class Epi>
+inline hipError_t launch_hex8(const MechGrid &M, const T *const x[3], Epi epi, double *partials, const DevScalars *sc,
+                              hipStream_t s) {
+  const int kc = cell_kchunk(M.g);
+  hipLaunchKernelGGL((hex8_cell_kernel<T, NS, Epi>), cell_grid(M.g, kc), dim3(CX, CY), 0, s, M, x[0], x[1], x[2], kc,
+                     epi, partials, sc);
+  return hipGetLastError();
 }
 
 }  // namespace mech

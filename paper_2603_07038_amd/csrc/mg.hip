@@ -99,17 +99,6 @@ __device__ __forceinline__ void stencil_apply(const MgLevel<T> &L, int i, int j,
   y[0] = y0; y[1] = y1; y[2] = y2;
 }
 
-template <typename T, bool MF>
-__device__ __forceinline__ void level_apply(const MechGrid &M, const MgLevel<T> &L, int i, int j, int k, int64_t n,
-                                            const V3<T> &x, T y[3]) {
-  if constexpr (MF) {
-    const T *pv[3] = {x.c[0], x.c[1], x.c[2]};
-    node_apply<T>(M, i, j, k, n, pv, y[0], y[1], y[2]);
-  } else {
-    stencil_apply<T>(L, i, j, k, n, x, y);
-  }
-}
-
 // Inverse of the live part of a symmetric 3x3 block (dead rows/columns zero).
 // out = (xx, yy, zz, xy, yz, xz).
 __device__ __forceinline__ void inv3_live(const double Bin[9], uint8_t dead, double out[6]) {
@@ -400,15 +389,15 @@ __global__ __launch_bounds__(256) void mg_start_kernel(MgLevel<T> L, V3<T> v) {
 }
 
 // w = Dinv A (scale * v); partial sums of |w|^2.
-template <typename T, bool MF>
-__global__ __launch_bounds__(256) void mg_power_kernel(MechGrid M, MgLevel<T> L, V3<T> v, V3<T> w,
+template <typename T>
+__global__ __launch_bounds__(256) void mg_power_kernel(MgLevel<T> L, V3<T> v, V3<T> w,
                                                        const double *scale, double *partials) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   double ww = 0.0;
   if (i <= L.nx && j <= L.ny) {
     const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
     T y[3];
-    level_apply<T, MF>(M, L, i, j, k, n, v, y);
+    stencil_apply<T>(L, i, j, k, n, v, y);
     const T s = T(*scale);
     const int64_t N = L.n;
     const T d00 = L.Dinv[n], d11 = L.Dinv[N + n], d22 = L.Dinv[2 * N + n];
@@ -440,10 +429,23 @@ __global__ void mg_scalar_set(double *p, double v) {
 
 // ---- V-cycle --------------------------------------------------------------------
 
+// First Chebyshev step from x = 0 at node n: d = x = c2 Dinv b.
+template <typename T>
+__device__ __forceinline__ void first_step(const MgLevel<T> &L, int64_t n, T b0, T b1, T b2, T c2) {
+  const int64_t N = L.n;
+  const T d00 = L.Dinv[n], d11 = L.Dinv[N + n], d22 = L.Dinv[2 * N + n];
+  const T d01 = L.Dinv[3 * N + n], d12 = L.Dinv[4 * N + n], d02 = L.Dinv[5 * N + n];
+  const T z0 = c2 * (d00 * b0 + d01 * b1 + d02 * b2);
+  const T z1 = c2 * (d01 * b0 + d11 * b1 + d12 * b2);
+  const T z2 = c2 * (d02 * b0 + d12 * b1 + d22 * b2);
+  L.d.c[0][n] = z0; L.d.c[1][n] = z1; L.d.c[2][n] = z2;
+  L.xa.c[0][n] = z0; L.xa.c[1][n] = z1; L.xa.c[2][n] = z2;
+}
+
 // One Chebyshev step: r = b - A x_in (r = b when first: x_in = 0),
 // d = c1 d + c2 Dinv r, x_out = x_in + d.
-template <typename T, bool MF>
-__global__ __launch_bounds__(256) void mg_smooth_kernel(MechGrid M, MgLevel<T> L, V3<T> b, V3<T> xin, V3<T> xout,
+template <typename T>
+__global__ __launch_bounds__(256) void mg_smooth_kernel(MgLevel<T> L, V3<T> b, V3<T> xin, V3<T> xout,
                                                         T c1, T c2, int first, const DevScalars *sc) {
   if (sc && sc->done) return;
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
@@ -454,7 +456,7 @@ __global__ __launch_bounds__(256) void mg_smooth_kernel(MechGrid M, MgLevel<T> L
     r[0] = b.c[0][n]; r[1] = b.c[1][n]; r[2] = b.c[2][n];
   } else {
     T y[3];
-    level_apply<T, MF>(M, L, i, j, k, n, xin, y);
+    stencil_apply<T>(L, i, j, k, n, xin, y);
     r[0] = b.c[0][n] - y[0]; r[1] = b.c[1][n] - y[1]; r[2] = b.c[2][n] - y[2];
   }
   const int64_t N = L.n;
@@ -472,22 +474,24 @@ __global__ __launch_bounds__(256) void mg_smooth_kernel(MechGrid M, MgLevel<T> L
 }
 
 // r = b - A x.
-template <typename T, bool MF>
-__global__ __launch_bounds__(256) void mg_resid_kernel(MechGrid M, MgLevel<T> L, V3<T> b, V3<T> x, V3<T> r,
+template <typename T>
+__global__ __launch_bounds__(256) void mg_resid_kernel(MgLevel<T> L, V3<T> b, V3<T> x, V3<T> r,
                                                        const DevScalars *sc) {
   if (sc && sc->done) return;
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   T y[3];
-  level_apply<T, MF>(M, L, i, j, k, n, x, y);
+  stencil_apply<T>(L, i, j, k, n, x, y);
 #pragma unroll
   for (int c = 0; c < 3; ++c) r.c[c][n] = b.c[c][n] - y[c];
 }
 
-// b_C = P^T r_F (one thread per coarse node).
+// b_C = P^T r_F (one thread per coarse node).  With smooth != 0 the coarse
+// level's first Chebyshev step (x = 0, so pointwise) follows at once:
+// d_C = x_C = c2 Dinv_C b_C.
 template <typename T>
-__global__ __launch_bounds__(256) void mg_restrict_kernel(MgLevel<T> F, V3<T> r, MgLevel<T> C,
+__global__ __launch_bounds__(256) void mg_restrict_kernel(MgLevel<T> F, V3<T> r, MgLevel<T> C, int smooth, T c2,
                                                           const DevScalars *sc) {
   if (sc && sc->done) return;
   const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
@@ -513,9 +517,11 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(MgLevel<T> F, V3<T> r,
   }
   const int64_t cn = int64_t(K) * C.sz + int64_t(J) * C.sy + I;
   const uint8_t dd = C.dead[cn];
-  C.b.c[0][cn] = (dd & 1) ? T(0) : T(a0);
-  C.b.c[1][cn] = (dd & 2) ? T(0) : T(a1);
-  C.b.c[2][cn] = (dd & 4) ? T(0) : T(a2);
+  const T b0 = (dd & 1) ? T(0) : T(a0), b1 = (dd & 2) ? T(0) : T(a1), b2 = (dd & 4) ? T(0) : T(a2);
+  C.b.c[0][cn] = b0;
+  C.b.c[1][cn] = b1;
+  C.b.c[2][cn] = b2;
+  if (smooth) first_step<T>(C, cn, b0, b1, b2, c2);
 }
 
 // x_F += P x_C on the live DOFs of F (one thread per fine node).
@@ -556,43 +562,114 @@ __global__ __launch_bounds__(256) void mg_zero_kernel(MgLevel<T> L, V3<T> x, con
   x.c[0][n] = T(0); x.c[1][n] = T(0); x.c[2][n] = T(0);
 }
 
-// Coarsest level: x[live] = Ainv b[live] (Ainv symmetric, read by columns).
+// Coarsest level: x[live] = Ainv b[live] (Ainv symmetric, read by
+// columns).  b[live] is staged in LDS; each block owns 32 rows and splits
+// every row's sum over 8 thread groups, reduced in a fixed order.
+constexpr int kDenseRows = 32, kDenseParts = 8;
 template <typename T>
 __global__ __launch_bounds__(256) void mg_dense_kernel(const T *Ainv, const int32_t *live, int nl, V3<T> b, V3<T> x,
                                                        const DevScalars *sc) {
   if (sc && sc->done) return;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nl) return;
-  double acc = 0.0;
-  for (int j = 0; j < nl; ++j) {
+  extern __shared__ double bs[];
+  __shared__ double red[kDenseParts][kDenseRows];
+  for (int j = threadIdx.x; j < nl; j += blockDim.x) {
     const int code = live[j];
-    acc += double(Ainv[int64_t(j) * nl + r]) * double(b.c[code % 3][code / 3]);
+    bs[j] = double(b.c[code % 3][code / 3]);
   }
-  const int cr = live[r];
-  x.c[cr % 3][cr / 3] = T(acc);
+  __syncthreads();
+  const int lane = threadIdx.x % kDenseRows, part = threadIdx.x / kDenseRows;
+  const int r = blockIdx.x * kDenseRows + lane;
+  double acc = 0.0;
+  if (r < nl)
+    for (int j = part; j < nl; j += kDenseParts) acc += double(Ainv[int64_t(j) * nl + r]) * bs[j];
+  red[part][lane] = acc;
+  __syncthreads();
+  if (part == 0 && r < nl) {
+    double sum = red[0][lane];
+#pragma unroll
+    for (int q = 1; q < kDenseParts; ++q) sum += red[q][lane];
+    const int cr = live[r];
+    x.c[cr % 3][cr / 3] = T(sum);
+  }
 }
 
-// ---- CG with the V-cycle ------------------------------------------------------------
+// ---- level 0 on the cell-based HEX8 apply -----------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void cgmg_start_kernel(MechGrid M, CgVecs<T> v, const T *b0, const T *b1,
-                                                         const T *b2, double *partials) {
-  const DevGrid &g = M.g;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  double rr = 0.0;
-  if (i <= g.nx && j <= g.ny) {
-    const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
-    const T *pv[3] = {v.u[0], v.u[1], v.u[2]};
-    T y0, y1, y2;
-    node_apply<T>(M, i, j, k, n, pv, y0, y1, y2);
-    const T r0 = b0[n] - y0, r1 = b1[n] - y1, r2 = b2[n] - y2;
-    v.r[0][n] = r0; v.r[1][n] = r1; v.r[2][n] = r2;
-    rr = double(r0) * double(r0) + double(r1) * double(r1) + double(r2) * double(r2);
-  }
-  const double s[1] = {rr};
-  const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  block_sums<1>(s, partials + b * kRedWidth);
+__device__ __forceinline__ void dinv_mul(const MgLevel<T> &L, int64_t n, const T r[3], T z[3]) {
+  const int64_t N = L.n;
+  const T d00 = L.Dinv[n], d11 = L.Dinv[N + n], d22 = L.Dinv[2 * N + n];
+  const T d01 = L.Dinv[3 * N + n], d12 = L.Dinv[4 * N + n], d02 = L.Dinv[5 * N + n];
+  z[0] = d00 * r[0] + d01 * r[1] + d02 * r[2];
+  z[1] = d01 * r[0] + d11 * r[1] + d12 * r[2];
+  z[2] = d02 * r[0] + d12 * r[1] + d22 * r[2];
 }
+
+// Chebyshev step on level 0 (x_in = the applied vector): r = b - K x_in,
+// d = c1 d + c2 Dinv r, x_out = x_in + d.
+template <typename T>
+struct EpiSmooth0 {
+  MgLevel<T> L;
+  V3<T> b, xout;
+  T c1, c2;
+  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T xc[3], double *) const {
+    const T r[3] = {b.c[0][n] - y[0], b.c[1][n] - y[1], b.c[2][n] - y[2]};
+    T z[3];
+    dinv_mul<T>(L, n, r, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T dn = c2 * z[c];
+      if (c1 != T(0)) dn += c1 * L.d.c[c][n];
+      L.d.c[c][n] = dn;
+      xout.c[c][n] = xc[c] + dn;
+    }
+  }
+};
+
+template <typename T>
+struct EpiResid0 {
+  V3<T> b, r;
+  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T *, double *) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r.c[c][n] = b.c[c][n] - y[c];
+  }
+};
+
+template <typename T>
+struct EpiPower0 {
+  MgLevel<T> L;
+  V3<T> w;
+  const double *scale;
+  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T *, double *red) const {
+    T z[3];
+    dinv_mul<T>(L, n, y, z);
+    const T s = T(*scale);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      z[c] *= s;
+      w.c[c][n] = z[c];
+      red[0] += double(z[c]) * double(z[c]);
+    }
+  }
+};
+
+// CG start on level 0: r = b - K u, |r|^2, and the first smoothing step.
+template <typename T>
+struct EpiStart0 {
+  CgVecs<T> v;
+  const T *b0, *b1, *b2;
+  MgLevel<T> L0;
+  int smooth;
+  T c2;
+  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T *, double *red) const {
+    const T r0 = b0[n] - y[0], r1 = b1[n] - y[1], r2 = b2[n] - y[2];
+    v.r[0][n] = r0; v.r[1][n] = r1; v.r[2][n] = r2;
+    red[0] += double(r0) * double(r0) + double(r1) * double(r1) + double(r2) * double(r2);
+    if (smooth) first_step<T>(L0, n, r0, r1, r2, c2);
+  }
+};
+
+// ---- CG with the V-cycle ------------------------------------------------------------
 
 __global__ void cgmg_start_finalize(const double *part, int64_t nb, DevScalars *sc) {
   __shared__ double out[1];
@@ -651,20 +728,24 @@ __global__ __launch_bounds__(256) void cgmg_p_kernel(CgVecs<T> v, V3<T> z, int64
   }
 }
 
+// u += alpha p, r -= alpha w, |r|^2; with smooth != 0 also the level-0
+// first Chebyshev step on r (padding entries have Dinv = 0).
 template <typename T>
-__global__ __launch_bounds__(256) void cgmg_update_kernel(CgVecs<T> v, int64_t ntot, const DevScalars *sc,
-                                                          double *partials) {
+__global__ __launch_bounds__(256) void cgmg_update_kernel(CgVecs<T> v, int64_t ntot, MgLevel<T> L0, int smooth, T c2,
+                                                          const DevScalars *sc, double *partials) {
   if (sc->done) return;
   const T alpha = T(sc->alpha);
   double rr = 0.0;
   for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < ntot; n += int64_t(gridDim.x) * blockDim.x) {
+    T r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       v.u[c][n] += alpha * v.p[c][n];
-      const T r = v.r[c][n] - alpha * v.w[c][n];
-      v.r[c][n] = r;
-      rr += double(r) * double(r);
+      r[c] = v.r[c][n] - alpha * v.w[c][n];
+      v.r[c][n] = r[c];
+      rr += double(r[c]) * double(r[c]);
     }
+    if (smooth) first_step<T>(L0, n, r[0], r[1], r[2], c2);
   }
   const double s[1] = {rr};
   block_sums<1>(s, partials + int64_t(blockIdx.x) * kRedWidth);
@@ -699,41 +780,45 @@ hipError_t smooth(const MgDev<T> &G, int l, V3<T> b, V3<T> xin, V3<T> xout, int 
                   const DevScalars *sc, hipStream_t s) {
   const MgLevel<T> &L = G.L[l];
   const T c1 = T(L.c1[step]), c2 = T(L.c2[step]);
-  if (l == 0)
-    hipLaunchKernelGGL((mg_smooth_kernel<T, true>), lgrid(L), dim3(BX, BY), 0, s, G.M, L, b, xin, xout, c1, c2, first,
-                       sc);
-  else
-    hipLaunchKernelGGL((mg_smooth_kernel<T, false>), lgrid(L), dim3(BX, BY), 0, s, G.M, L, b, xin, xout, c1, c2,
-                       first, sc);
+  if (l == 0 && !first)
+    return launch_hex8<T, 0>(G.M, xin.c, EpiSmooth0<T>{L, b, xout, c1, c2}, nullptr, sc, s);
+  hipLaunchKernelGGL((mg_smooth_kernel<T>), lgrid(L), dim3(BX, BY), 0, s, L, b, xin, xout, c1, c2, first, sc);
   return hipGetLastError();
 }
 
+// Coarse levels get their first smoothing step inside the restriction, and
+// level 0 inside the CG kernel that forms r (first_done).
 template <typename T>
-hipError_t vcycle_level(const MgDev<T> &G, int l, V3<T> b, const DevScalars *sc, V3<T> *out, hipStream_t s) {
+hipError_t vcycle_level(const MgDev<T> &G, int l, V3<T> b, const DevScalars *sc, V3<T> *out, hipStream_t s,
+                        bool first_done) {
   const MgLevel<T> &L = G.L[l];
   hipError_t e;
   if (l == G.nlev - 1) {
     hipLaunchKernelGGL((mg_zero_kernel<T>), lgrid(L), dim3(BX, BY), 0, s, L, L.xa, sc);
-    hipLaunchKernelGGL((mg_dense_kernel<T>), dim3((G.nlive + 255) / 256), dim3(256), 0, s, (const T *)G.Ainv,
-                       (const int32_t *)G.live, G.nlive, b, L.xa, sc);
+    if (G.nlive > 0)
+      hipLaunchKernelGGL((mg_dense_kernel<T>), dim3((G.nlive + kDenseRows - 1) / kDenseRows), dim3(256),
+                         size_t(G.nlive) * sizeof(double), s, (const T *)G.Ainv, (const int32_t *)G.live, G.nlive, b,
+                         L.xa, sc);
     *out = L.xa;
     return hipGetLastError();
   }
   V3<T> xc = L.xa, xo = L.xb;
-  if ((e = smooth(G, l, b, xo, xc, 0, 1, sc, s)) != hipSuccess) return e;
+  if (!first_done && (e = smooth(G, l, b, xo, xc, 0, 1, sc, s)) != hipSuccess) return e;
   for (int k = 1; k < kMgDeg; ++k) {
     if ((e = smooth(G, l, b, xc, xo, k, 0, sc, s)) != hipSuccess) return e;
     std::swap(xc, xo);
   }
-  if (l == 0)
-    hipLaunchKernelGGL((mg_resid_kernel<T, true>), lgrid(L), dim3(BX, BY), 0, s, G.M, L, b, xc, xo, sc);
-  else
-    hipLaunchKernelGGL((mg_resid_kernel<T, false>), lgrid(L), dim3(BX, BY), 0, s, G.M, L, b, xc, xo, sc);
+  if (l == 0) {
+    if ((e = launch_hex8<T, 0>(G.M, xc.c, EpiResid0<T>{b, xo}, nullptr, sc, s)) != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL((mg_resid_kernel<T>), lgrid(L), dim3(BX, BY), 0, s, L, b, xc, xo, sc);
+  }
   const MgLevel<T> &C = G.L[l + 1];
-  hipLaunchKernelGGL((mg_restrict_kernel<T>), lgrid(C), dim3(BX, BY), 0, s, L, xo, C, sc);
+  const int fuse = l + 2 < G.nlev;  // the coarse level smooths (it is not the coarsest)
+  hipLaunchKernelGGL((mg_restrict_kernel<T>), lgrid(C), dim3(BX, BY), 0, s, L, xo, C, fuse, T(C.c2[0]), sc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   V3<T> xcoarse;
-  if ((e = vcycle_level(G, l + 1, C.b, sc, &xcoarse, s)) != hipSuccess) return e;
+  if ((e = vcycle_level(G, l + 1, C.b, sc, &xcoarse, s, fuse != 0)) != hipSuccess) return e;
   hipLaunchKernelGGL((mg_prolong_kernel<T>), lgrid(L), dim3(BX, BY), 0, s, L, xc, C, xcoarse, sc);
   for (int k = 0; k < kMgDeg; ++k) {
     if ((e = smooth(G, l, b, xc, xo, k, 0, sc, s)) != hipSuccess) return e;
@@ -778,14 +863,16 @@ hipError_t launch_mg_power(const MgDev<T> &G, int l, int iters, double *partials
   hipLaunchKernelGGL((mg_start_kernel<T>), lgrid(L), dim3(BX, BY), 0, s, L, L.xa);
   hipLaunchKernelGGL(mg_scalar_set, dim3(1), dim3(64), 0, s, G.scale, 1.0);
   V3<T> v = L.xa, w = L.xb;
+  const int64_t nb = l == 0 ? cell_blocks(G.M.g, cell_kchunk(G.M.g)) : lblocks(L);
   for (int it = 0; it < iters; ++it) {
-    if (l == 0)
-      hipLaunchKernelGGL((mg_power_kernel<T, true>), lgrid(L), dim3(BX, BY), 0, s, G.M, L, v, w,
-                         (const double *)G.scale, partials);
-    else
-      hipLaunchKernelGGL((mg_power_kernel<T, false>), lgrid(L), dim3(BX, BY), 0, s, G.M, L, v, w,
-                         (const double *)G.scale, partials);
-    hipLaunchKernelGGL(mg_power_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, lblocks(L), G.lam + l,
+    if (l == 0) {
+      hipError_t e = launch_hex8<T, 1>(G.M, v.c, EpiPower0<T>{L, w, (const double *)G.scale}, partials, nullptr, s);
+      if (e != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL((mg_power_kernel<T>), lgrid(L), dim3(BX, BY), 0, s, L, v, w, (const double *)G.scale,
+                         partials);
+    }
+    hipLaunchKernelGGL(mg_power_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, G.lam + l,
                        G.scale);
     std::swap(v, w);
   }
@@ -794,7 +881,7 @@ hipError_t launch_mg_power(const MgDev<T> &G, int l, int iters, double *partials
 
 template <typename T>
 hipError_t launch_mg_vcycle(const MgDev<T> &G, V3<T> b, const DevScalars *sc, V3<T> *z, hipStream_t s) {
-  return vcycle_level(G, 0, b, sc, z, s);
+  return vcycle_level(G, 0, b, sc, z, s, false);
 }
 
 template <typename T>
@@ -802,11 +889,15 @@ hipError_t launch_cgmg_setup(const MgDev<T> &G, const CgVecs<T> &v, const T *rhs
                              DevScalars *sc, hipStream_t s) {
   const MgLevel<T> &L0 = G.L[0];
   const int64_t nb = lblocks(L0);
-  hipLaunchKernelGGL((cgmg_start_kernel<T>), lgrid(L0), dim3(BX, BY), 0, s, G.M, v, rhs[0], rhs[1], rhs[2],
-                     partials);
-  hipLaunchKernelGGL(cgmg_start_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc);
+  const int fuse = G.nlev > 1;
+  const T *u[3] = {v.u[0], v.u[1], v.u[2]};
+  hipError_t e0 = launch_hex8<T, 1>(G.M, u, EpiStart0<T>{v, rhs[0], rhs[1], rhs[2], L0, fuse, T(L0.c2[0])}, partials,
+                                    nullptr, s);
+  if (e0 != hipSuccess) return e0;
+  hipLaunchKernelGGL(cgmg_start_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
+                     cell_blocks(G.M.g, cell_kchunk(G.M.g)), sc);
   V3<T> r{{v.r[0], v.r[1], v.r[2]}}, z;
-  hipError_t e = vcycle_level(G, 0, r, sc, &z, s);
+  hipError_t e = vcycle_level(G, 0, r, sc, &z, s, fuse != 0);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((cgmg_dot_kernel<T>), lgrid(L0), dim3(BX, BY), 0, s, G.M, v, z, (const DevScalars *)sc,
                      partials);
@@ -824,11 +915,12 @@ hipError_t launch_cgmg_iteration(const MgDev<T> &G, const CgVecs<T> &v, double *
   hipError_t e = launch_cg_apply_alpha<T>(G.M, v, partials, sc, s);
   if (e != hipSuccess) return e;
   const int fb = flat_blocks(L0.n);
-  hipLaunchKernelGGL((cgmg_update_kernel<T>), dim3(fb), dim3(256), 0, s, v, L0.n, (const DevScalars *)sc,
-                     partials);
+  const int fuse = G.nlev > 1;
+  hipLaunchKernelGGL((cgmg_update_kernel<T>), dim3(fb), dim3(256), 0, s, v, L0.n, L0, fuse, T(L0.c2[0]),
+                     (const DevScalars *)sc, partials);
   hipLaunchKernelGGL(cgmg_rr_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, int64_t(fb), sc);
   V3<T> r{{v.r[0], v.r[1], v.r[2]}}, z;
-  if ((e = vcycle_level(G, 0, r, sc, &z, s)) != hipSuccess) return e;
+  if ((e = vcycle_level(G, 0, r, sc, &z, s, fuse != 0)) != hipSuccess) return e;
   hipLaunchKernelGGL((cgmg_dot_kernel<T>), lgrid(L0), dim3(BX, BY), 0, s, G.M, v, z, (const DevScalars *)sc,
                      partials);
   hipLaunchKernelGGL(cgmg_rz_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc, 0);

@@ -414,6 +414,7 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   take(p->r_hist, size_t(p->hist_cap) * p->hist_cols * 8);
   for (int c = 0; c < 3; ++c) {
     take(p->r_u64[c], N * 8); take(p->r_f64[c], N * 8); take(p->r_r64[c], N * 8); take(p->r_dinv64[c], N * 8);
+    take(p->r_uprev64[c], N * 8);
   }
   if (p->prec == ETM_PREC_FP64) {
     for (int c = 0; c < 3; ++c) { take(p->r_p64[c], N * 8); take(p->r_w64[c], N * 8); }
@@ -900,6 +901,19 @@ etm_status mech_solve_impl(etm_plan *p) {
       for (int c = 0; c < 3; ++c) HIP_TRY(launch_vec_cast(dinv64[c], 0, p->ptr<float>(p->r_dinv32[c]), 1, N, p->stream));
     p->dinv_ready = true;
   }
+  // Initial guess: the last solution, extrapolated linearly in time through
+  // the one before it (thermal-step counts of the two solves).  Only the
+  // starting point of CG changes; convergence is still judged on the FP64
+  // residual of the new system.
+  double *uprev[3];
+  for (int c = 0; c < 3; ++c) uprev[c] = p->ptr<double>(p->r_uprev64[c]);
+  const int64_t tn = p->n_thermal;
+  if (p->sol_t[0] >= 0 && tn != p->sol_t[0]) {
+    const double sc = (p->sol_t[1] >= 0 && p->sol_t[0] > p->sol_t[1])
+                          ? double(tn - p->sol_t[0]) / double(p->sol_t[0] - p->sol_t[1]) : 0.0;
+    HIP_TRY(launch_extrapolate(u64, uprev, sc, N, p->stream));
+  }
+  if (tn != p->sol_t[0]) { p->sol_t[1] = p->sol_t[0]; p->sol_t[0] = tn; }
   const double *theta = p->ptr<double>(p->r_theta[p->th_cur]);
   HIP_TRY(launch_mech_rhs(M, theta, f64, p->ptr<double>(p->r_part), p->sc(), p->opts.cg_rtol, p->stream));
   if ((st = poll_scalars(p)) != ETM_OK) return st;
@@ -943,7 +957,7 @@ etm_status mech_solve_impl(etm_plan *p) {
       v.w[c] = p->ptr<float>(p->r_w32[c]); v.dinv[c] = p->ptr<float>(p->r_dinv32[c]);
       rhs32[c] = p->ptr<float>(p->r_rhs32[c]);
     }
-    const double inner_rtol = 1e-4;
+    const double inner_rtol = 1e-5;
     for (outer = 0; outer < 50;) {
       HIP_TRY(launch_residual64(M, cf64, cu64, r64, p->ptr<double>(p->r_part), p->sc(), p->stream));
       ++outer;
@@ -1086,6 +1100,7 @@ etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->step = 0; p->cur = 0; p->th_cur = 0; p->rec = 0; p->n_thermal = 0;
   p->n_solves = 0; p->cg_iters = 0; p->cg_outer = 0; p->cg_total = 0; p->cg_relres = 0;
+  p->sol_t[0] = p->sol_t[1] = -1;
   p->host_status = ETM_OK;
   p->dinv_ready = false;
   p->mg_ready = false;
@@ -1237,6 +1252,7 @@ struct CkptHeader {
   int64_t step, rec, n_thermal, cg_total;
   int32_t cur, th_cur, prec, n_solves;
   int64_t ntot;
+  int64_t sol_t[2];
 };
 constexpr uint64_t kMagic = 0x45544d434b505431ull;
 
@@ -1253,6 +1269,7 @@ std::vector<const Region *> state_regions(const etm_plan *p) {
   r.push_back(&p->r_sc);
   r.push_back(&p->r_hist);
   for (int c = 0; c < 3; ++c) r.push_back(&p->r_u64[c]);
+  for (int c = 0; c < 3; ++c) r.push_back(&p->r_uprev64[c]);
   return r;
 }
 }  // namespace
@@ -1271,7 +1288,8 @@ etm_status etm_checkpoint(const etm_plan *p, void *dst, size_t bytes) {
   size_t need = 0;
   etm_checkpoint_size(p, &need);
   if (bytes < need) return fail(ETM_E_NOMEM, "checkpoint buffer too small");
-  CkptHeader h{kMagic, p->step, p->rec, p->n_thermal, p->cg_total, p->cur, p->th_cur, p->prec, p->n_solves, p->ntot};
+  CkptHeader h{kMagic, p->step, p->rec, p->n_thermal, p->cg_total, p->cur, p->th_cur, p->prec, p->n_solves, p->ntot,
+               {p->sol_t[0], p->sol_t[1]}};
   char *o = static_cast<char *>(dst);
   std::memcpy(o, &h, sizeof(h));
   o += sizeof(h);
@@ -1300,6 +1318,7 @@ etm_status etm_restore(etm_plan *p, const void *src, size_t bytes) {
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->step = h.step; p->rec = h.rec; p->n_thermal = h.n_thermal; p->cg_total = h.cg_total;
   p->cur = h.cur; p->th_cur = h.th_cur; p->n_solves = h.n_solves;
+  p->sol_t[0] = h.sol_t[0]; p->sol_t[1] = h.sol_t[1];
   p->host_status = ETM_OK;
   p->joule_pending = false;
   return coef_refresh(p);
