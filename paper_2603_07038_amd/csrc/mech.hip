@@ -118,9 +118,13 @@ template <typename T>
 struct EpiJacobiStart {
   CgVecs<T> v;
   const T *b0, *b1, *b2;
-  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T *, double *red) const {
-    const T rx = b0[n] - y[0], ry = b1[n] - y[1], rz = b2[n] - y[2];
-    const T zx = v.dinv[0][n] * rx, zy = v.dinv[1][n] * ry, zz = v.dinv[2][n] * rz;
+  struct Pre { T b[3], d[3]; };
+  __device__ Pre load(int64_t n) const {
+    return Pre{{b0[n], b1[n], b2[n]}, {v.dinv[0][n], v.dinv[1][n], v.dinv[2][n]}};
+  }
+  __device__ void operator()(int64_t n, const T y[3], const T *, const Pre &q, double *red) const {
+    const T rx = q.b[0] - y[0], ry = q.b[1] - y[1], rz = q.b[2] - y[2];
+    const T zx = q.d[0] * rx, zy = q.d[1] * ry, zz = q.d[2] * rz;
     v.r[0][n] = rx; v.r[1][n] = ry; v.r[2][n] = rz;
     v.p[0][n] = zx; v.p[1][n] = zy; v.p[2][n] = zz;
     red[0] += double(rx) * double(zx) + double(ry) * double(zy) + double(rz) * double(zz);
@@ -144,7 +148,9 @@ __global__ __launch_bounds__(256) void cg_setup_finalize(const double *part, int
 template <typename T>
 struct EpiApplyDot {
   T *w0, *w1, *w2;
-  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T xc[3], double *red) const {
+  struct Pre {};
+  __device__ Pre load(int64_t) const { return Pre{}; }
+  __device__ void operator()(int64_t n, const T y[3], const T xc[3], const Pre &, double *red) const {
     w0[n] = y[0]; w1[n] = y[1]; w2[n] = y[2];
     red[0] += double(xc[0]) * double(y[0]) + double(xc[1]) * double(y[1]) + double(xc[2]) * double(y[2]);
   }
@@ -213,8 +219,10 @@ __global__ __launch_bounds__(256) void cg_p_kernel(CgVecs<T> v, int64_t ntot, co
 struct EpiResidual64 {
   const double *f0, *f1, *f2;
   double *r0, *r1, *r2;
-  __device__ void operator()(int, int, int, int64_t n, const double y[3], const double *, double *red) const {
-    const double rx = f0[n] - y[0], ry = f1[n] - y[1], rz = f2[n] - y[2];
+  struct Pre { double f[3]; };
+  __device__ Pre load(int64_t n) const { return Pre{{f0[n], f1[n], f2[n]}}; }
+  __device__ void operator()(int64_t n, const double y[3], const double *, const Pre &q, double *red) const {
+    const double rx = q.f[0] - y[0], ry = q.f[1] - y[1], rz = q.f[2] - y[2];
     r0[n] = rx; r1[n] = ry; r2[n] = rz;
     red[0] += rx * rx + ry * ry + rz * rz;
   }

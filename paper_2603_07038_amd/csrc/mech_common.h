@@ -149,8 +149,10 @@ __device__ __forceinline__ void hex8_cell(T ux[8], T uy[8], T uz[8], T hx, T hy,
 // next node plane of x in LDS (three-plane ring), every thread applies its
 // cell's K_e and stores the 24 results in LDS, and each owned node adds the
 // corners of its four cells in a fixed order, so y is deterministic.
-// Fixed DOFs give zero rows; x is taken as zero on them.  The epilogue sees
-// (i, j, k, n, y, x at the node, per-thread partial sums).
+// Fixed DOFs give zero rows; x is taken as zero on them.  The next x plane
+// and the epilogue's own inputs (Epi::load, issued before the cell work)
+// are fetched one layer ahead.  The epilogue sees (n, y, x at the node, its
+// prefetched inputs, per-thread partial sums).
 constexpr int CX = 32, CY = 8;
 
 inline dim3 cell_grid(const DevGrid &g, int kchunk) {
@@ -168,6 +170,8 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
                                                              const DevScalars *sc) {
   if (sc && sc->done) return;
   const DevGrid &g = M.g;
+  constexpr int PL = (CY + 1) * (CX + 1);          // nodes per staged plane
+  constexpr int PT = (PL + CX * CY - 1) / (CX * CY);  // plane entries per thread
   __shared__ T xs[3][3][CY + 1][CX + 1];
   __shared__ T co[24][CY][CX];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * CX + tx;
@@ -182,21 +186,43 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
   double red[NS > 0 ? NS : 1];
 #pragma unroll
   for (int q = 0; q < (NS > 0 ? NS : 1); ++q) red[q] = 0.0;
-  auto load_plane = [&](int k) {
-    T(*dst)[CY + 1][CX + 1] = xs[(k + 3) % 3];
-    for (int t = tid; t < (CY + 1) * (CX + 1); t += CX * CY) {
+  // plane k of x into registers (this thread's share), then into LDS
+  T pf[PT][3];
+  auto fetch = [&](int k) {
+#pragma unroll
+    for (int e = 0; e < PT; ++e) {
+      const int t = tid + e * CX * CY;
       const int r = t / (CX + 1), c = t - r * (CX + 1);
       const int i = i0 - 1 + c, j = j0 - 1 + r;
-      const bool ok = k >= 0 && k <= g.nz && i >= 0 && i <= g.nx && j >= 0 && j <= g.ny;
+      const bool ok = t < PL && k >= 0 && k <= g.nz && i >= 0 && i <= g.nx && j >= 0 && j <= g.ny;
       const int64_t n = ok ? int64_t(k) * g.sz + int64_t(j) * g.sy + i : 0;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) dst[q][r][c] = ok ? xv[q][n] : T(0);
+      for (int q = 0; q < 3; ++q) pf[e][q] = ok ? xv[q][n] : T(0);
+    }
+  };
+  auto stage = [&](int k) {
+    T(*dst)[CY + 1][CX + 1] = xs[(k + 3) % 3];
+#pragma unroll
+    for (int e = 0; e < PT; ++e) {
+      const int t = tid + e * CX * CY;
+      if (t < PL) {
+        const int r = t / (CX + 1), c = t - r * (CX + 1);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) dst[q][r][c] = pf[e][q];
+      }
     }
   };
   T acc[3] = {T(0), T(0), T(0)};
-  load_plane(k0 - 1);
+  fetch(k0 - 1);
+  stage(k0 - 1);
+  fetch(k0);
   for (int ck = k0 - 1; ck < k1; ++ck) {
-    load_plane(ck + 1);
+    stage(ck + 1);        // plane ck + 1 (fetched during the previous layer)
+    if (ck + 2 <= k1) fetch(ck + 2);  // in flight while this layer computes
+    const int64_t n = int64_t(ck) * g.sz + int64_t(nj) * g.sy + ni;
+    const bool emit = own && ck >= k0;
+    typename Epi::Pre pre;
+    if (emit) pre = epi.load(n);
     __syncthreads();
     T ux[8], uy[8], uz[8];
     bool live = cin && ck >= 0 && ck < g.nz;
@@ -240,15 +266,14 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
         top[q] = co[7 * 3 + q][ty][tx] + co[6 * 3 + q][ty][tx + 1] + co[5 * 3 + q][ty + 1][tx] +
                  co[4 * 3 + q][ty + 1][tx + 1];
       }
-      if (ck >= k0) {
-        const int64_t n = int64_t(ck) * g.sz + int64_t(nj) * g.sy + ni;
+      if (emit) {
         const uint8_t f = M.fixed[n];
         if (f & 1) y[0] = T(0);
         if (f & 2) y[1] = T(0);
         if (f & 4) y[2] = T(0);
         const T(*pl)[CY + 1][CX + 1] = xs[(ck + 3) % 3];
         const T xc[3] = {pl[0][ty + 1][tx + 1], pl[1][ty + 1][tx + 1], pl[2][ty + 1][tx + 1]};
-        epi(ni, nj, ck, n, y, xc, red);
+        epi(n, y, xc, pre, red);
       }
 #pragma unroll
       for (int q = 0; q < 3; ++q) acc[q] = top[q];

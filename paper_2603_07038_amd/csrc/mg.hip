@@ -595,31 +595,44 @@ __global__ __launch_bounds__(256) void mg_dense_kernel(const T *Ainv, const int3
 
 // ---- level 0 on the cell-based HEX8 apply -----------------------------------------
 
-template <typename T>
-__device__ __forceinline__ void dinv_mul(const MgLevel<T> &L, int64_t n, const T r[3], T z[3]) {
-  const int64_t N = L.n;
-  const T d00 = L.Dinv[n], d11 = L.Dinv[N + n], d22 = L.Dinv[2 * N + n];
-  const T d01 = L.Dinv[3 * N + n], d12 = L.Dinv[4 * N + n], d02 = L.Dinv[5 * N + n];
-  z[0] = d00 * r[0] + d01 * r[1] + d02 * r[2];
-  z[1] = d01 * r[0] + d11 * r[1] + d12 * r[2];
-  z[2] = d02 * r[0] + d12 * r[1] + d22 * r[2];
-}
-
 // Chebyshev step on level 0 (x_in = the applied vector): r = b - K x_in,
 // d = c1 d + c2 Dinv r, x_out = x_in + d.
+template <typename T>
+__device__ __forceinline__ void dinv_load(const MgLevel<T> &L, int64_t n, T D[6]) {
+#pragma unroll
+  for (int e = 0; e < 6; ++e) D[e] = L.Dinv[e * L.n + n];
+}
+
+template <typename T>
+__device__ __forceinline__ void dinv_apply(const T D[6], const T r[3], T z[3]) {
+  z[0] = D[0] * r[0] + D[3] * r[1] + D[5] * r[2];
+  z[1] = D[3] * r[0] + D[1] * r[1] + D[4] * r[2];
+  z[2] = D[5] * r[0] + D[4] * r[1] + D[2] * r[2];
+}
+
 template <typename T>
 struct EpiSmooth0 {
   MgLevel<T> L;
   V3<T> b, xout;
   T c1, c2;
-  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T xc[3], double *) const {
-    const T r[3] = {b.c[0][n] - y[0], b.c[1][n] - y[1], b.c[2][n] - y[2]};
-    T z[3];
-    dinv_mul<T>(L, n, r, z);
+  struct Pre { T b[3], D[6], d[3]; };
+  __device__ Pre load(int64_t n) const {
+    Pre q;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      T dn = c2 * z[c];
-      if (c1 != T(0)) dn += c1 * L.d.c[c][n];
+      q.b[c] = b.c[c][n];
+      q.d[c] = c1 != T(0) ? L.d.c[c][n] : T(0);
+    }
+    dinv_load<T>(L, n, q.D);
+    return q;
+  }
+  __device__ void operator()(int64_t n, const T y[3], const T xc[3], const Pre &q, double *) const {
+    const T r[3] = {q.b[0] - y[0], q.b[1] - y[1], q.b[2] - y[2]};
+    T z[3];
+    dinv_apply<T>(q.D, r, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T dn = c2 * z[c] + c1 * q.d[c];
       L.d.c[c][n] = dn;
       xout.c[c][n] = xc[c] + dn;
     }
@@ -629,9 +642,11 @@ struct EpiSmooth0 {
 template <typename T>
 struct EpiResid0 {
   V3<T> b, r;
-  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T *, double *) const {
+  struct Pre { T b[3]; };
+  __device__ Pre load(int64_t n) const { return Pre{{b.c[0][n], b.c[1][n], b.c[2][n]}}; }
+  __device__ void operator()(int64_t n, const T y[3], const T *, const Pre &q, double *) const {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) r.c[c][n] = b.c[c][n] - y[c];
+    for (int c = 0; c < 3; ++c) r.c[c][n] = q.b[c] - y[c];
   }
 };
 
@@ -640,9 +655,15 @@ struct EpiPower0 {
   MgLevel<T> L;
   V3<T> w;
   const double *scale;
-  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T *, double *red) const {
+  struct Pre { T D[6]; };
+  __device__ Pre load(int64_t n) const {
+    Pre q;
+    dinv_load<T>(L, n, q.D);
+    return q;
+  }
+  __device__ void operator()(int64_t n, const T y[3], const T *, const Pre &q, double *red) const {
     T z[3];
-    dinv_mul<T>(L, n, y, z);
+    dinv_apply<T>(q.D, y, z);
     const T s = T(*scale);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -661,8 +682,10 @@ struct EpiStart0 {
   MgLevel<T> L0;
   int smooth;
   T c2;
-  __device__ void operator()(int, int, int, int64_t n, const T y[3], const T *, double *red) const {
-    const T r0 = b0[n] - y[0], r1 = b1[n] - y[1], r2 = b2[n] - y[2];
+  struct Pre { T b[3]; };
+  __device__ Pre load(int64_t n) const { return Pre{{b0[n], b1[n], b2[n]}}; }
+  __device__ void operator()(int64_t n, const T y[3], const T *, const Pre &q, double *red) const {
+    const T r0 = q.b[0] - y[0], r1 = q.b[1] - y[1], r2 = q.b[2] - y[2];
     v.r[0][n] = r0; v.r[1][n] = r1; v.r[2][n] = r2;
     red[0] += double(r0) * double(r0) + double(r1) * double(r1) + double(r2) * double(r2);
     if (smooth) first_step<T>(L0, n, r0, r1, r2, c2);
