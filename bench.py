@@ -13,7 +13,20 @@ included; the march-only rate and CG DOF-iterations/s are reported beside
 it.  The headline runs the mixed path (FP32 fields, FP64 temperature /
 Joule / CG refinement); the same blocks are timed on the FP64 path.
 
+Beside the headline, the same JSON line carries:
+  fullscale  the 1024x1024x128 package (134 M cells): EM march rate and its
+             HBM roofline fraction, mixed and FP64;
+  batch      64 design variants of uneven size (64x64x32 .. 192x192x48,
+             2048 EM steps + a mechanical solve each): one batched mixed run
+             against 64 sequential FP64 runs and a batched FP64 run, with
+             the largest temperature / peak von Mises difference between the
+             mixed and FP64 results;
+  serving    Poisson arrivals of design requests (sizes log-uniform between
+             32^3 and 512x512x64 cells) through the continuous-batching
+             server: p50/p99 latency and designs/hour, mixed and FP64.
+
     python bench.py [--steps K] [--warmup W] [--precision mixed|fp64] [--no-fp64] [--no-cpu]
+                    [--legs coupled,fullscale,batch,serve] [--serve-requests N] [--serve-rate R]
 """
 from __future__ import annotations
 
@@ -30,9 +43,11 @@ HBM_PEAK_GBS = 8000.0
 # Compulsory bytes per cell-step of the fused EM step (one cell ~ one node +
 # three edges): FP64 e^n, e^{n-1} read + e^{n+1} written (72), material id
 # (1), temperature for sigma(T) (8), Joule accumulator read-modify-write (16);
-# mixed: e, delta read + written in FP32 (48), id (1), FP32 temperature (4),
-# Joule RMW (16).
-BYTES_PER_CELL_STEP = {"fp64": 97.0, "mixed": 69.0}
+# mixed (leapfrog form): e in FP32 read + written (24) with its 8-bit
+# residual (6), face field h in FP32 read + written (24), the sigma-change
+# correction K read (12, plans with temperature-dependent conductors), id (1),
+# FP32 temperature (4), Joule RMW (16).
+BYTES_PER_CELL_STEP = {"fp64": 97.0, "mixed": 87.0}
 # Compulsory bytes per DOF-iteration of Jacobi-PCG (vectors u, r, p, w and the
 # inverse diagonal streamed once per iteration): FP64 80, FP32 40.
 BYTES_PER_DOF_ITER = {"fp64": 80.0, "mixed": 40.0}
@@ -47,6 +62,10 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--legs", default="coupled,fullscale,batch,serve")
+    ap.add_argument("--batch-variants", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-rate", type=float, default=2.0)
     ap.add_argument("--probe", choices=["em", "em-fp64", "copy"], default=None,
                     help="short runs for hardware-counter profiles: 20 EM steps of the workload, or a plain "
                          "2 GiB device copy (the calibration kernel for FETCH_SIZE / WRITE_SIZE)")
@@ -146,6 +165,7 @@ def run_precision(prob, J, dt, prec_name, steps, warmup):
     )
     bpc = BYTES_PER_CELL_STEP[prec_name]
     achieved = bpc * cells / em_launch_s / 1e9
+    res["fields"] = (plan.read(etm.ETM_FIELD_THETA), plan.read(etm.ETM_FIELD_VM))
     res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(prec_name),
                        "traffic_unit": "bytes/launch", "algorithmic_bytes_per_launch": int(bpc * cells),
@@ -154,6 +174,124 @@ def run_precision(prob, J, dt, prec_name, steps, warmup):
                        "bytes_per_cell_step": bpc, "cells_per_launch": cells}
     del plan
     torch.cuda.synchronize()
+    return res
+
+
+def fullscale_leg(steps=48, warmup=8):
+    """EM march of the 1024x1024x128 package, mixed and FP64."""
+    import torch
+    import workloads as W
+    import paper_2603_07038_amd as etm
+    prob = W.config3()
+    prob.history_stride = 0
+    dt = etm.cfl_dt(prob)
+    J = prob.sample_J_half(dt, steps + warmup + 2)
+    out = {"workload": prob.name, "cells": prob.n_cells}
+    for name, prec in (("mixed", etm.ETM_PREC_MIXED), ("fp64", etm.ETM_PREC_FP64)):
+        plan = etm.Plan(prob, J, dt=dt, precision=prec, n_steps=steps + warmup + 2, history=False)
+        plan.advance(warmup)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(plan.stream)
+        plan.advance(steps)
+        e1.record(plan.stream)
+        plan.sync()
+        t = e0.elapsed_time(e1) / 1e3 / steps
+        bpc = BYTES_PER_CELL_STEP[name]
+        gbs = bpc * prob.n_cells / t / 1e9
+        out[name] = {"march_mcell_steps_per_s": round(prob.n_cells / t / 1e6, 1), "em_kernel_us": round(t * 1e6, 1),
+                     "achieved_GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        del plan
+        torch.cuda.synchronize()
+    return out
+
+
+def batch_leg(n_variants):
+    """The 64-variant batch: batched mixed vs sequential FP64 (and batched FP64)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2603_07038_amd as etm
+    probs = [W.config4_variant(v) for v in range(n_variants)]
+    dts = [etm.cfl_dt(p) for p in probs]
+    Js = [p.sample_J_half(dt, p.n_em_steps) for p, dt in zip(probs, dts)]
+    steps = probs[0].n_em_steps
+    assert all(p.n_em_steps == steps for p in probs)
+    cell_steps = sum(p.n_cells for p in probs) * steps
+    res = {"variants": n_variants, "em_steps": steps, "cells_total": sum(p.n_cells for p in probs)}
+    fields = {}
+
+    def batched(prec):
+        plans = [etm.Plan(p, J, dt=dt, precision=prec, n_steps=steps, history=False, stream=torch.cuda.Stream())
+                 for p, J, dt in zip(probs, Js, dts)]
+        b = etm.Batch(len(plans))
+        for pl in plans:
+            b.attach(pl)
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        b.advance(steps, s)
+        s.synchronize()
+        infos = etm.solve_all(plans)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        out = [(pl.read(etm.ETM_FIELD_THETA), pl.read(etm.ETM_FIELD_VM)) for pl in plans]
+        del b, plans
+        torch.cuda.synchronize()
+        return wall, out, infos
+
+    def sequential(prec):
+        wall = 0.0
+        out = []
+        for p, J, dt in zip(probs, Js, dts):
+            pl = etm.Plan(p, J, dt=dt, precision=prec, n_steps=steps, history=False)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            pl.advance(steps)
+            pl.mech_solve()
+            pl.sync()
+            wall += time.perf_counter() - t
+            out.append((pl.read(etm.ETM_FIELD_THETA), pl.read(etm.ETM_FIELD_VM)))
+            del pl
+        torch.cuda.synchronize()
+        return wall, out
+
+    wb, fields["mixed"], _ = batched(etm.ETM_PREC_MIXED)
+    ws, fields["fp64"] = sequential(etm.ETM_PREC_FP64)
+    wbf, _, _ = batched(etm.ETM_PREC_FP64)
+    th_err = max(float(np.abs(a[0] - b[0]).max() / max(np.abs(b[0]).max(), 1e-300))
+                 for a, b in zip(fields["mixed"], fields["fp64"]))
+    vm_err = max(abs(float(a[1].max()) - float(b[1].max())) / max(float(b[1].max()), 1e-300)
+                 for a, b in zip(fields["mixed"], fields["fp64"]))
+    res.update({"batched_mixed_s": round(wb, 3), "sequential_fp64_s": round(ws, 3), "batched_fp64_s": round(wbf, 3),
+                "speedup_vs_sequential_fp64": round(ws / wb, 2),
+                "batched_mixed_mcell_steps_per_s": round(cell_steps / wb / 1e6, 1),
+                "sequential_fp64_mcell_steps_per_s": round(cell_steps / ws / 1e6, 1),
+                "theta_rel_err_mixed_vs_fp64": th_err, "peak_vm_rel_err_mixed_vs_fp64": vm_err,
+                "timing": "wall clock, EM march + thermal + one mechanical solve per variant; plan set-up excluded"})
+    return res
+
+
+def serve_leg(n_requests, rate):
+    """Continuous-batching server under Poisson arrivals, mixed and FP64."""
+    import torch
+    import workloads as W
+    import paper_2603_07038_amd as etm
+    from paper_2603_07038_amd import serve
+    arrivals = W.poisson_arrivals(rate, n_requests)
+    probs = [W.config5_request(r) for r in range(n_requests)]
+    res = {"requests": n_requests, "rate_per_s": rate,
+           "mean_cells": round(sum(p.n_cells for p in probs) / n_requests), "arrivals": "Poisson, seed 5999"}
+    for name, prec in (("mixed", etm.ETM_PREC_MIXED), ("fp64", etm.ETM_PREC_FP64)):
+        reqs = [serve.Request(p, float(t), r) for r, (p, t) in enumerate(zip(probs, arrivals))]
+        srv = serve.Server(max_slots=16, hbm_budget=96e9, precision=prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        done = srv.run(reqs, realtime=True)
+        wall = time.perf_counter() - t
+        summ = serve.summarize(done, wall)
+        res[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+        del srv
+        torch.cuda.synchronize()
     return res
 
 
@@ -186,6 +324,7 @@ def main():
     import torch
     import workloads as W
     import paper_2603_07038_amd as etm
+    legs = set(a.legs.split(","))
     prob = W.config2()
     dt = etm.cfl_dt(prob)
     J = prob.sample_J_half(dt, prob.n_em_steps)
@@ -194,6 +333,13 @@ def main():
     other = None
     if not a.no_fp64 and a.precision == "mixed":
         other = run_precision(prob, J, dt, "fp64", a.steps, a.warmup)
+    extra = {}
+    if "fullscale" in legs:
+        extra["fullscale"] = fullscale_leg()
+    if "batch" in legs:
+        extra["batch"] = batch_leg(a.batch_variants)
+    if "serve" in legs:
+        extra["serving"] = serve_leg(a.serve_requests, a.serve_rate)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(prob, dt, J, a.cpu_seconds)
@@ -222,7 +368,16 @@ def main():
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
     }
+    out.update(extra)
     if other:
+        import numpy as np
+        (tm, vm), (tf, vf) = head.pop("fields"), other.pop("fields")
+        out["mixed_vs_fp64"] = {
+            "theta_rel_err": float(np.abs(tm - tf).max() / max(np.abs(tf).max(), 1e-300)),
+            "peak_vm_rel_err": abs(float(vm.max()) - float(vf.max())) / max(float(vf.max()), 1e-300),
+            "theta_max_K": float(tf.max()),
+            "after_em_steps": (a.warmup + a.steps) * prob.em_per_thermal,
+            "targets": {"theta": 1e-6, "peak_vm": 1e-5}}
         out["fp64"] = {"value": round(other["value"], 2), "ms_per_step": round(other["ms_per_step"], 3),
                        "march_mcell_steps_per_s": round(other["march_mcell_steps_per_s"], 1),
                        "em_kernel_us": round(other["em_kernel_us"], 2), "cg_iters": other["cg_iters"],

@@ -49,7 +49,11 @@ enum {
 
 enum { ETM_PMC = 0, ETM_PEC = 1 };                          /* EM face condition */
 enum { ETM_MECH_KINEMATIC = 0, ETM_MECH_CLAMP_ZMIN = 1 };   /* mechanical support */
-enum { ETM_PREC_FP64 = 0, ETM_PREC_MIXED = 1 };             /* arithmetic of the path */
+/* Arithmetic of the path.  FP64: the three-level update of Eq. (2)-(3) on
+ * (e^n, e^{n-1}) in FP64.  MIXED: the same scheme in its leapfrog form on
+ * (e^n, h^{n-1/2}), both stored in FP32 and combined in FP64, with FP64
+ * temperature, Joule accumulation and CG refinement. */
+enum { ETM_PREC_FP64 = 0, ETM_PREC_MIXED = 1 };
 /* Preconditioner of the mechanical CG (Eq. 8): nodal Jacobi, or a geometric
  * multigrid V-cycle with Galerkin coarse operators (the role the paper's
  * algebraic multigrid plays, Sec. 4.1). */
@@ -128,6 +132,9 @@ typedef struct {
     int32_t mech_precond;       /* ETM_PRECOND_MG (default) or ETM_PRECOND_JACOBI */
     int32_t mg_coarse_dofs;     /* multigrid: coarsen until a level has at most this many DOF
                                    (solved with a dense inverse; default 800, range 3..4000) */
+    int32_t mg_degree[2];       /* multigrid: Chebyshev smoothing steps before and after the coarse
+                                   correction on the finest level and on the coarser levels
+                                   (0 = default 2; range 1..4) */
 } etm_opts;
 
 /* What etm_sync reports. */
@@ -197,7 +204,10 @@ etm_status etm_sync(etm_plan *plan, etm_run_info *info);
  * field's size * 8).  dst_is_device != 0: dst is device memory. */
 etm_status etm_read(const etm_plan *plan, int32_t field, void *dst, size_t bytes, int32_t dst_is_device);
 
-/* Overwrite a state field (EX..PSUM, UX..UZ) from FP64 natural-shape data. */
+/* Overwrite a state field (EX..PSUM, UX..UZ) from FP64 natural-shape data.
+ * The mixed path advances e with its face field h (leapfrog form), so its
+ * e fields (EX..EZ_PREV) are not writable there (ETM_E_INVAL); checkpoints
+ * restore them together with h. */
 etm_status etm_write(etm_plan *plan, int32_t field, const void *src, size_t bytes, int32_t src_is_device);
 
 /* Histories: rows of [step, W, cumulative Joule energy, max theta, probes...]

@@ -58,7 +58,7 @@ class etm_opts(C.Structure):
                 ("mech_bc", C.c_int32), ("mech_mask", C.POINTER(C.c_uint8)), ("cg_maxit", C.c_int32),
                 ("cg_rtol", C.c_double), ("history_stride", C.c_int32), ("n_probes", C.c_int32),
                 ("probes", C.POINTER(C.c_int64)), ("history_cap", C.c_int64), ("n_em_steps_hint", C.c_int64),
-                ("mech_precond", C.c_int32), ("mg_coarse_dofs", C.c_int32)]
+                ("mech_precond", C.c_int32), ("mg_coarse_dofs", C.c_int32), ("mg_degree", C.c_int32 * 2)]
 
 
 class etm_run_info(C.Structure):
@@ -315,12 +315,34 @@ class Plan:
         check(load().etm_restore(self.h, buf.ctypes.data, buf.nbytes))
 
 
+def solve_all(plans, workers=4):
+    """Mechanical solves of several bound plans at once.  Each solve runs from
+    a worker thread on its plan's own stream (the library releases the GIL
+    while it waits), so the small solves of a batch overlap on the GPU.
+    Returns each plan's run info."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(pl):
+        pl.mech_solve()
+        return pl.sync()
+
+    with ThreadPoolExecutor(max_workers=max(1, int(workers))) as ex:
+        return list(ex.map(one, plans))
+
+
 class Batch:
     """Several bound plans advanced together (etm_batch_*): one launch per EM
     step over all variants, chunks of steps replayed from HIP graphs."""
 
     def __init__(self, max_slots, tune_json=None):
+        """tune_json: the autotuner's table (JSON text); None reads the table
+        committed next to this file, if any ("{}" for built-in defaults)."""
         h = _P()
+        if tune_json is None:
+            path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_gfx950.json")
+            if os.path.exists(path):
+                with open(path) as f:
+                    tune_json = f.read()
         tj = None if tune_json is None else tune_json.encode()
         check(load().etm_batch_create(int(max_slots), tj, C.byref(h)))
         self.h = h

@@ -91,7 +91,11 @@ int size_class(const etm_plan *p) {
   return int(std::floor(std::log2(std::max(cells, 1.0))));
 }
 
+// New work list after attach / detach.  Kernels and graph launches of the
+// previous work list may still be running on the batch's own (non-blocking)
+// stream: drain it before the list, the graphs or their buffers change.
 etm_status rebuild(etm_batch *b) {
+  HIP_TRY(hipStreamSynchronize(b->run));
   b->order.clear();
   for (int s = 0; s < b->max_slots; ++s)
     if (b->slots[s]) b->order.push_back(s);
@@ -115,7 +119,10 @@ etm_status rebuild(etm_batch *b) {
     HIP_TRY(hipMalloc((void **)&b->d_items, std::max<size_t>(items.size(), 1) * sizeof(int4)));
     b->items_cap = items.size();
   }
-  if (!items.empty()) HIP_TRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
+  if (!items.empty()) {
+    HIP_TRY(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, b->run));
+    HIP_TRY(hipStreamSynchronize(b->run));
+  }
   b->n_items = int(items.size());
   drop_graphs(b);
   b->dirty = false;
@@ -137,7 +144,7 @@ etm_status stage_vars(etm_batch *b, hipStream_t st) {
       for (int d = 0; d < 3; ++d) V.e[q][d] = p->r_e[q][d].bytes ? p->ws + p->r_e[q][d].off : nullptr;
     if (p->prec == ETM_PREC_MIXED)
       for (int q = 0; q < 2; ++q)
-        for (int d = 0; d < 3; ++d) V.d[q][d] = p->ws + p->r_d[q][d].off;
+        for (int d = 0; d < 3; ++d) V.h[q][d] = p->ws + p->r_h[q][d].off;
     V.theta[0] = p->ptr<double>(p->r_theta[0]);
     V.theta[1] = p->ptr<double>(p->r_theta[1]);
     V.theta32 = p->prec == ETM_PREC_MIXED ? p->ptr<float>(p->r_theta32) : nullptr;
@@ -325,6 +332,7 @@ etm_status etm_batch_advance(etm_batch *b, int64_t n, void *stream) {
 
 void etm_batch_destroy(etm_batch *b) {
   if (!b) return;
+  if (b->run) (void)hipStreamSynchronize(b->run);
   drop_graphs(b);
   for (int q = 0; q < kStageRing; ++q)
     if (b->stage_ev[q]) {

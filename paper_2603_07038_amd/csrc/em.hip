@@ -45,16 +45,6 @@ struct GAcc {  // global memory around node n
   __device__ __forceinline__ double operator()(int c, int di, int dj, int dk) const { return double(raw(c, di, dj, dk)); }
 };
 template <typename T>
-struct GDiff {  // a - b (e^n recovered from e^{n+1} and delta)
-  const T *a[3], *b[3];
-  int64_t n, sy, sz;
-  __device__ __forceinline__ T raw(int c, int di, int dj, int dk) const {
-    const int64_t q = n + di + dj * sy + dk * sz;
-    return a[c][q] - b[c][q];
-  }
-  __device__ __forceinline__ double operator()(int c, int di, int dj, int dk) const { return double(raw(c, di, dj, dk)); }
-};
-template <typename T>
 struct SAcc {  // LDS ring: slot[dk+1] holds plane k+dk
   const T (*sh)[3][TYH][TXH];
   int slot[3];
@@ -229,11 +219,14 @@ __device__ __forceinline__ int find_port(const DevPorts &P, int64_t key) {
 }
 
 // Source and lumped conductance of the port edge (key) at this step.
+// Port source of EM step n at an edge: jd = dt (J^{n+1/2} - J^{n-1/2}) / eps0
+// (three-level form), jn = dt J^{n+1/2} / eps0 (leapfrog form), and the
+// lumped conductance g (scaled like the a-coefficient).
 struct PortTerm {
-  double jd, g;
+  double jd, jn, g;
 };
 __device__ __forceinline__ PortTerm port_terms(const DevPorts &P, int64_t key, int64_t step) {
-  PortTerm r{0.0, 0.0};
+  PortTerm r{0.0, 0.0, 0.0};
   const int q = find_port(P, key);
   if (q < 0) return r;
   r.g = P.gs[q];
@@ -242,8 +235,36 @@ __device__ __forceinline__ PortTerm port_terms(const DevPorts &P, int64_t key, i
     const double *Jw = P.J + int64_t(P.wave[t]) * ns;
     const double j1 = s1 < ns ? Jw[s1] : 0.0, j0 = s0 < ns ? Jw[s0] : 0.0;
     r.jd += P.wt[t] * (j1 - j0);
+    r.jn += P.wt[t] * j1;
   }
   return r;
+}
+
+// The mixed path keeps each e component as an FP32 value plus an 8-bit
+// residual: e = hi + lo * ulp(hi) / 256.  The stencil reads hi; the own-edge
+// accumulation e^{n+1} = e^n + (e^{n+1} - e^n) runs on the full value, so
+// the per-step rounding of e (which otherwise dominates the error of the
+// temperature rise over long windows) is 256 times smaller.
+__device__ __forceinline__ double ulp32(float h) {
+  const int E = int((__float_as_uint(h) >> 23) & 0xFFu);
+  return ldexp(1.0, max(E, 1) - 150);
+}
+__device__ __forceinline__ double e_join(float hi, int8_t lo) { return double(hi) + double(lo) * (ulp32(hi) * (1.0 / 256.0)); }
+__device__ __forceinline__ void e_split(double x, float &hi, int8_t &lo) {
+  hi = float(x);
+  const double r = rint((x - double(hi)) / ulp32(hi) * 256.0);
+  lo = int8_t(fmax(-128.0, fmin(127.0, r)));
+}
+
+// Face value of the leapfrog field h^{n+1/2} = h^{n-1/2} + c0 dt (curl e^n)
+// (per unit area), from the face's four edge values in the fixed order
+// (a - b) s + (c - d) t.  Every thread that needs a face computes it with
+// this one expression, so a face computed at a tile or chunk border is
+// bitwise the value its owner stores.
+__device__ __forceinline__ float hface(float hold, float a, float b, double s, float c, float d, double t,
+                                       double cdt) {
+  const double q = __builtin_fma(double(a) - double(b), s, (double(c) - double(d)) * t);
+  return float(__builtin_fma(cdt, q, double(hold)));
 }
 
 // 1/x in FP64: hardware reciprocal and two Newton steps (full precision).
@@ -265,9 +286,9 @@ struct MarchSmem {
 template <typename T>
 struct EmPtrs {
   const T *e;    // e^n (component c at + c*cs)
-  const T *aux;  // FP64: e^{n-1};  mixed: delta^{n-1/2}
+  const T *aux;  // FP64: e^{n-1};  mixed: h^{n-1/2} (faces: x-normal, y-normal, z-normal at + c*cs)
   T *oe;         // e^{n+1}
-  T *oaux;       // mixed: delta^{n+1/2}
+  T *oaux;       // mixed: h^{n+1/2}
 };
 
 // Joule power density at node n from the stored coefficients of its six
@@ -289,7 +310,19 @@ __device__ __forceinline__ double joule_from_coef(const T *cf, uint32_t cs, uint
 // Per plane: stage e plane k+1, update the own edges of the nodes of plane
 // k from their stored coefficients, and gather the Joule power of e^n at the
 // node from its six incident edges.
-template <typename T, bool INC>
+// One z-march of a 64 x 4 column tile.  FP64 (YEE = false): the
+// three-level form of Eq. (2)-(3) on (e^n, e^{n-1}).  Mixed (YEE = true): the
+// same scheme written as leapfrog on (e^n, h^{n-1/2}), both stored in FP32
+// and combined in FP64:
+//   h^{n+1/2} = h^{n-1/2} + c0 dt curl e^n                       (faces)
+//   (er + a) (e^{n+1} - e^n) = -2a e^n - c0 dt curl^T h^{n+1/2} - jn + K
+// Eliminating h gives Eq. (2) exactly; K (per edge, zero until sigma changes)
+// carries the difference the three-level form keeps when a changes at a
+// thermal step.  Rounding errors of h reach e only through curl^T, so they
+// never feed the gradient (static-charge) modes the curl-curl leaves
+// undamped in dielectrics; the increment form e^{n+1} - e^n stored in FP32
+// lets them accumulate.
+template <typename T, bool YEE>
 __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T> &p, int64_t step, int tx, int ty,
                                               int kc, int kchunk, int acc_joule, MarchSmem<T> &S) {
   const DevGrid &g = L.g;
@@ -323,6 +356,8 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
   const int pec = g.pec;
   const bool pec_i = (i == 0 && (pec & 1)) || (i == nx && (pec & 2));
   const bool pec_j = (j == 0 && (pec & 4)) || (j == ny && (pec & 8));
+  // leapfrog form: the two faces below (k-1) carry over from the previous plane
+  float hy_prev = 0.0f, hx_prev = 0.0f;
   int s_m = 0, s_0 = 1, s_p = 2;
   load_plane(k0 - 1, s_m);
   load_plane(k0, s_0);
@@ -331,61 +366,118 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
     __syncthreads();
     if (active) {
       const uint32_t n = uint32_t(k) * sz + uint32_t(j) * sy + uint32_t(i);
-      const T idz_k = T(G.idz[min(k, nz - 1)]), idz_m = T(G.idz[max(k - 1, 0)]), ihz_k = T(G.ihz[k]);
-      const T vk0 = T(k > 0), vk1 = T(k < nz);
       const bool pec_k = (k == 0 && (pec & 16)) || (k == nz && (pec & 32));
       auto E = [&](int c, int di, int dj, int dk) -> T {
         const int sl = dk < 0 ? s_m : dk > 0 ? s_p : s_0;
         return S.e[sl][c][ly + 1 + dj][lx + 1 + di];
       };
       const uint8_t fl = (g.flags[n] & 7);
-      // curl-curl of e^n on the three own edges (faces outside the mesh masked to 0)
       const T e0x = E(0, 0, 0, 0), e0y = E(1, 0, 0, 0), e0z = E(2, 0, 0, 0);
-      const T hz_c = (e0x - E(0, 0, 1, 0)) * idy_j + (E(1, 1, 0, 0) - e0y) * idx_i;        // hz(i, j)
-      const T hy_c = (e0z - E(2, 1, 0, 0)) * idx_i + (E(0, 0, 0, 1) - e0x) * idz_k;        // hy(i, k)
-      const T hx_c = (E(2, 0, 1, 0) - e0z) * idy_j - (E(1, 0, 0, 1) - e0y) * idz_k;        // hx(j, k)
       const bool pec_d[3] = {pec_j || pec_k, pec_i || pec_k, pec_i || pec_j};
+      if constexpr (YEE) {
+        const double cdt = L.cdt;
+        const double dxi = G.idx[min(ic, nx - 1)], dxm = G.idx[max(ic - 1, 0)], dhx = G.ihx[ic];
+        const double dyj = G.idy[min(jc, ny - 1)], dym = G.idy[max(jc - 1, 0)], dhy = G.ihy[jc];
+        const double dzk = G.idz[min(k, nz - 1)], dzm = G.idz[max(k - 1, 0)], dhz = G.ihz[k];
+        const float *hi = reinterpret_cast<const float *>(p.aux);
+        float *ho = reinterpret_cast<float *>(p.oaux);
+        // own faces (x-normal hx, y-normal hy, z-normal hz at node n)
+        float hz_c = 0.0f, hy_c = 0.0f, hx_c = 0.0f;
+        if (i < nx && j < ny) hz_c = hface(hi[2 * cs + n], e0x, E(0, 0, 1, 0), dyj, E(1, 1, 0, 0), e0y, dxi, cdt);
+        if (i < nx && k < nz) hy_c = hface(hi[cs + n], e0z, E(2, 1, 0, 0), dxi, E(0, 0, 0, 1), e0x, dzk, cdt);
+        if (j < ny && k < nz) hx_c = hface(hi[n], E(2, 0, 1, 0), e0z, dyj, e0y, E(1, 0, 0, 1), dzk, cdt);
+        if (i < nx && j < ny) ho[2 * cs + n] = hz_c;
+        if (i < nx && k < nz) ho[cs + n] = hy_c;
+        if (j < ny && k < nz) ho[n] = hx_c;
+        // faces below in y and x (another thread's, recomputed identically)
+        float hz_jm = 0.0f, hx_jm = 0.0f, hz_im = 0.0f, hy_im = 0.0f, hy_km = 0.0f, hx_km = 0.0f;
+        if (j > 0 && i < nx)
+          hz_jm = hface(hi[2 * cs + n - sy], E(0, 0, -1, 0), e0x, dym, E(1, 1, -1, 0), E(1, 0, -1, 0), dxi, cdt);
+        if (j > 0 && k < nz)
+          hx_jm = hface(hi[n - sy], e0z, E(2, 0, -1, 0), dym, E(1, 0, -1, 0), E(1, 0, -1, 1), dzk, cdt);
+        if (i > 0 && j < ny)
+          hz_im = hface(hi[2 * cs + n - 1], E(0, -1, 0, 0), E(0, -1, 1, 0), dyj, e0y, E(1, -1, 0, 0), dxm, cdt);
+        if (i > 0 && k < nz)
+          hy_im = hface(hi[cs + n - 1], E(2, -1, 0, 0), e0z, dxm, E(0, -1, 0, 1), E(0, -1, 0, 0), dzk, cdt);
+        if (k > 0) {
+          if (k > k0) {
+            hy_km = hy_prev;
+            hx_km = hx_prev;
+          } else {
+            if (i < nx) hy_km = hface(hi[cs + n - sz], E(2, 0, 0, -1), E(2, 1, 0, -1), dxi, e0x, E(0, 0, 0, -1), dzm, cdt);
+            if (j < ny) hx_km = hface(hi[n - sz], E(2, 0, 1, -1), E(2, 0, 0, -1), dyj, E(1, 0, 0, -1), e0y, dzm, cdt);
+          }
+        }
+        hy_prev = hy_c;
+        hx_prev = hx_c;
+        const float *Kp = L.K;
 #pragma unroll
-      for (int D = 0; D < 3; ++D) {
-        const bool exists = D == 0 ? i < nx : D == 1 ? j < ny : k < nz;
-        if (!exists) continue;
-        const uint32_t o = D * cs + n;
-        if (pec_d[D]) {
-          p.oe[o] = T(0);
-          if (INC) p.oaux[o] = T(0);
-          continue;
-        }
-        T cc;
-        if (D == 0) {
-          const T hz_jm = (E(0, 0, -1, 0) - e0x) * idy_m + (E(1, 1, -1, 0) - E(1, 0, -1, 0)) * idx_i;
-          const T hy_km = (E(2, 0, 0, -1) - E(2, 1, 0, -1)) * idx_i + (e0x - E(0, 0, 0, -1)) * idz_m;
-          cc = (vj1 * hz_c - vj0 * hz_jm) * ihy_j - (vk1 * hy_c - vk0 * hy_km) * ihz_k;
-        } else if (D == 1) {
-          const T hx_km = (E(2, 0, 1, -1) - E(2, 0, 0, -1)) * idy_j - (e0y - E(1, 0, 0, -1)) * idz_m;
-          const T hz_im = (E(0, -1, 0, 0) - E(0, -1, 1, 0)) * idy_j + (e0y - E(1, -1, 0, 0)) * idx_m;
-          cc = (vk1 * hx_c - vk0 * hx_km) * ihz_k - (vi1 * hz_c - vi0 * hz_im) * ihx_i;
-        } else {
-          const T hy_im = (E(2, -1, 0, 0) - e0z) * idx_m + (E(0, -1, 0, 1) - E(0, -1, 0, 0)) * idz_k;
-          const T hx_jm = (e0z - E(2, 0, -1, 0)) * idy_m - (E(1, 0, -1, 1) - E(1, 0, -1, 0)) * idz_k;
-          cc = (vi1 * hy_c - vi0 * hy_im) * ihx_i - (vj1 * hx_c - vj0 * hx_jm) * ihy_j;
-        }
-        const T e0 = D == 0 ? e0x : D == 1 ? e0y : e0z;
-        if (INC) {
+        for (int D = 0; D < 3; ++D) {
+          const bool exists = D == 0 ? i < nx : D == 1 ? j < ny : k < nz;
+          if (!exists) continue;
+          const uint32_t o = D * cs + n;
+          if (pec_d[D]) {
+            p.oe[o] = T(0);
+            L.elo[o] = 0;
+            continue;
+          }
+          double cc;
+          if (D == 0)
+            cc = (double(hz_c) - double(hz_jm)) * dhy - (double(hy_c) - double(hy_km)) * dhz;
+          else if (D == 1)
+            cc = (double(hx_c) - double(hx_km)) * dhz - (double(hz_c) - double(hz_im)) * dhx;
+          else
+            cc = (double(hy_c) - double(hy_im)) * dhx - (double(hx_c) - double(hx_jm)) * dhy;
           // stored: 1/(er + a) and 2a, each rounded once from FP64
-          T inv = cf[D * cs + n], a2 = cf[(3 + D) * cs + n], jd = T(0);
+          double inv = double(cf[D * cs + n]), a2 = double(cf[(3 + D) * cs + n]), jn = 0.0;
           if (fl & (1 << D)) {
             const int q = find_port(L.ports, int64_t(D) * g.ntot + n);
             const PortTerm pt = port_terms(L.ports, int64_t(D) * g.ntot + n, step);
-            const double a = 0.5 * double(a2) + pt.g;
-            inv = T(rcp64(L.ports.er[q] + a));
-            a2 = T(2.0 * a);
-            jd = T(pt.jd);
+            const double a = 0.5 * a2 + pt.g;
+            inv = rcp64(L.ports.er[q] + a);
+            a2 = 2.0 * a;
+            jn = pt.jn;
           }
-          const T d0 = p.aux[o];
-          const T d1 = d0 - (a2 * d0 + c2 * cc + jd) * inv;
-          p.oaux[o] = d1;
-          p.oe[o] = e0 + d1;
-        } else {
+          const float e0h = D == 0 ? e0x : D == 1 ? e0y : e0z;
+          const double kk = Kp ? double(Kp[o]) : 0.0;
+          const double dl = -(a2 * double(e0h) + cdt * cc + jn - kk) * inv;
+          float eh;
+          int8_t el;
+          e_split(e_join(e0h, L.elo[o]) + dl, eh, el);
+          p.oe[o] = T(eh);
+          L.elo[o] = el;
+        }
+      } else {
+        const T idz_k = T(G.idz[min(k, nz - 1)]), idz_m = T(G.idz[max(k - 1, 0)]), ihz_k = T(G.ihz[k]);
+        const T vk0 = T(k > 0), vk1 = T(k < nz);
+        // curl-curl of e^n on the three own edges (faces outside the mesh masked to 0)
+        const T hz_c = (e0x - E(0, 0, 1, 0)) * idy_j + (E(1, 1, 0, 0) - e0y) * idx_i;        // hz(i, j)
+        const T hy_c = (e0z - E(2, 1, 0, 0)) * idx_i + (E(0, 0, 0, 1) - e0x) * idz_k;        // hy(i, k)
+        const T hx_c = (E(2, 0, 1, 0) - e0z) * idy_j - (E(1, 0, 0, 1) - e0y) * idz_k;        // hx(j, k)
+#pragma unroll
+        for (int D = 0; D < 3; ++D) {
+          const bool exists = D == 0 ? i < nx : D == 1 ? j < ny : k < nz;
+          if (!exists) continue;
+          const uint32_t o = D * cs + n;
+          if (pec_d[D]) {
+            p.oe[o] = T(0);
+            continue;
+          }
+          T cc;
+          if (D == 0) {
+            const T hz_jm = (E(0, 0, -1, 0) - e0x) * idy_m + (E(1, 1, -1, 0) - E(1, 0, -1, 0)) * idx_i;
+            const T hy_km = (E(2, 0, 0, -1) - E(2, 1, 0, -1)) * idx_i + (e0x - E(0, 0, 0, -1)) * idz_m;
+            cc = (vj1 * hz_c - vj0 * hz_jm) * ihy_j - (vk1 * hy_c - vk0 * hy_km) * ihz_k;
+          } else if (D == 1) {
+            const T hx_km = (E(2, 0, 1, -1) - E(2, 0, 0, -1)) * idy_j - (e0y - E(1, 0, 0, -1)) * idz_m;
+            const T hz_im = (E(0, -1, 0, 0) - E(0, -1, 1, 0)) * idy_j + (e0y - E(1, -1, 0, 0)) * idx_m;
+            cc = (vk1 * hx_c - vk0 * hx_km) * ihz_k - (vi1 * hz_c - vi0 * hz_im) * ihx_i;
+          } else {
+            const T hy_im = (E(2, -1, 0, 0) - e0z) * idx_m + (E(0, -1, 0, 1) - E(0, -1, 0, 0)) * idz_k;
+            const T hx_jm = (e0z - E(2, 0, -1, 0)) * idy_m - (E(1, 0, -1, 1) - E(1, 0, -1, 0)) * idz_k;
+            cc = (vi1 * hy_c - vi0 * hy_im) * ihx_i - (vj1 * hx_c - vj0 * hx_jm) * ihy_j;
+          }
+          const T e0 = D == 0 ? e0x : D == 1 ? e0y : e0z;
           T er = cf[D * cs + n], a = cf[(3 + D) * cs + n], jd = T(0);
           if (fl & (1 << D)) {
             const PortTerm pt = port_terms(L.ports, int64_t(D) * g.ntot + n, step);
@@ -417,20 +509,20 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * q + min(x, r) + pos;
 }
 
-template <typename T, bool INC>
+template <typename T, bool YEE>
 __global__ __launch_bounds__(256) void em_march_kernel(EmLaunch L, EmPtrs<T> p, int ntx, int nty, int nkc, int kchunk,
                                                        int acc_joule) {
   __shared__ MarchSmem<T> S;
   const int nb = ntx * nty * nkc;
   const int b = xcd_remap(blockIdx.x, nb);
   const int tx = b % ntx, ty = (b / ntx) % nty, kc = b / (ntx * nty);
-  em_march_tile<T, INC>(L, p, L.step, tx, ty, kc, kchunk, acc_joule, S);
+  em_march_tile<T, YEE>(L, p, L.step, tx, ty, kc, kchunk, acc_joule, S);
 }
 
 // ---- batched: one launch walks the (variant, tile) list of all variants ----
 // Item = (variant, tile x, tile y, z chunk).  The step offset s is read from
 // device memory so that a captured chunk of steps can be replayed.
-template <typename T, bool INC>
+template <typename T, bool YEE>
 __global__ __launch_bounds__(256) void em_march_batched(const BatchVar *vars, const int4 *items, int n_items,
                                                         const int64_t *step_ctr) {
   __shared__ MarchSmem<T> S;
@@ -440,12 +532,12 @@ __global__ __launch_bounds__(256) void em_march_batched(const BatchVar *vars, co
   const int64_t s = *step_ctr;
   const int64_t step = V.step0 + s;
   EmPtrs<T> p;
-  if (INC) {
+  if (YEE) {
     const int cur = int((V.cur0 + s) & 1), o = 1 - cur;
     p.e = (const T *)V.e[cur][0];
-    p.aux = (const T *)V.d[cur][0];
+    p.aux = (const T *)V.h[cur][0];
     p.oe = (T *)V.e[o][0];
-    p.oaux = (T *)V.d[o][0];
+    p.oaux = (T *)V.h[o][0];
   } else {
     const int cur = int((V.cur0 + s) % 3), prv = (cur + 2) % 3, nxt = (cur + 1) % 3;
     p.e = (const T *)V.e[cur][0];
@@ -454,7 +546,7 @@ __global__ __launch_bounds__(256) void em_march_batched(const BatchVar *vars, co
     p.oaux = nullptr;
   }
   const int acc = (s == 0) ? V.acc_joule0 : int(step % V.R != 0);
-  em_march_tile<T, INC>(V.L, p, step, it.y, it.z, it.w, V.kchunk, acc, S);
+  em_march_tile<T, YEE>(V.L, p, step, it.y, it.z, it.w, V.kchunk, acc, S);
 }
 
 __global__ void step_ctr_kernel(int64_t *ctr, int64_t v, int set) {
@@ -515,7 +607,7 @@ __device__ __forceinline__ double pending_joule(const DevGrid &g, const T *const
 // material conductance a = dt sigma(T) / (2 eps0), formed in FP64 from the
 // cells around the node and stored at the field precision.
 template <typename T>
-__global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const T *th, T *cf) {
+__global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const T *th, T *cf, CoefK ck) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i > g.nx || j > g.ny) return;
   const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
@@ -532,8 +624,19 @@ __global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const 
   for (int d = 0; d < 3; ++d) {
     const double e = er[d] > 0.0 ? er[d] : 1.0;  // a missing edge keeps a harmless 1
     if (sizeof(T) == 4) {
+      const float a2 = float(2.0 * a[d]);
+      if (ck.K) {
+        // leapfrog form: a changed from a_old to a between e_prev = e^{n-1}
+        // and e_cur = e^n; K += (a - a_old) (e^n + e^{n-1})
+        const float a2o = float(cf[(3 + d) * cs + n]);
+        if (a2 != a2o) {
+          const uint32_t o = d * cs + uint32_t(n);
+          ck.K[o] = float(double(ck.K[o]) +
+                          0.5 * (double(a2) - double(a2o)) * (double(ck.e_cur[o]) + double(ck.e_prev[o])));
+        }
+      }
       cf[d * cs + n] = T(1.0 / (e + a[d]));
-      cf[(3 + d) * cs + n] = T(2.0 * a[d]);
+      cf[(3 + d) * cs + n] = T(a2);
     } else {
       cf[d * cs + n] = T(e);
       cf[(3 + d) * cs + n] = T(a[d]);
@@ -650,7 +753,7 @@ __global__ __launch_bounds__(256) void thermal_finalize(const double *part, int6
 
 // ---- diagnostics -------------------------------------------------------------
 // W = eps0/(2 dt^2) sum_e L A [ er delta^2 + (c0 dt)^2 e^{n+1} (C e^n) ]
-template <typename T, bool INC>
+template <typename T>
 __global__ __launch_bounds__(256) void diag_kernel(DiagLaunch L) {
   const DevGrid &g = L.g;
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
@@ -671,18 +774,13 @@ __global__ __launch_bounds__(256) void diag_kernel(DiagLaunch L) {
     for (int D = 0; D < 3; ++D) {
       if ((D == 0 && i == g.nx) || (D == 1 && j == g.ny) || (D == 2 && k == g.nz)) continue;
       if (pec_edge(g, D, i, j, k)) continue;
-      double cc;
-      if (INC) {
-        GDiff<T> E{{en[0], en[1], en[2]}, {eo[0], eo[1], eo[2]}, n, g.sy, g.sz};
-        cc = D == 0 ? double(curl_x<T>(g, E, i, j, k)) : D == 1 ? double(curl_y<T>(g, E, i, j, k)) : double(curl_z<T>(g, E, i, j, k));
-      } else {
-        GAcc<T> E{{eo[0], eo[1], eo[2]}, n, g.sy, g.sz};
-        cc = D == 0 ? double(curl_x<T>(g, E, i, j, k)) : D == 1 ? double(curl_y<T>(g, E, i, j, k)) : double(curl_z<T>(g, E, i, j, k));
-      }
+      GAcc<T> E{{eo[0], eo[1], eo[2]}, n, g.sy, g.sz};
+      const double cc = D == 0 ? double(curl_x<T>(g, E, i, j, k))
+                               : D == 1 ? double(curl_y<T>(g, E, i, j, k)) : double(curl_z<T>(g, E, i, j, k));
       const double Lh = D == 0 ? g.dx[i] : D == 1 ? g.dy[j] : g.dz[k];
       const double A = D == 0 ? g.hy[j] * g.hz[k] : D == 1 ? g.hx[i] * g.hz[k] : g.hx[i] * g.hy[j];
       const double e1 = double(en[D][n]);
-      const double dl = INC ? double(eo[D][n]) : e1 - double(eo[D][n]);
+      const double dl = e1 - double(eo[D][n]);
       acc += Lh * A * (er3[D] * dl * dl + L.c2dt2 * e1 * cc);
     }
     w_part = acc;
@@ -822,13 +920,13 @@ hipError_t launch_joule_flush(const DevGrid &g, int precision, const void *const
   return hipGetLastError();
 }
 
-hipError_t launch_coef(const DevGrid &g, const DevPorts &P, int precision, const void *theta, void *coef,
+hipError_t launch_coef(const DevGrid &g, const DevPorts &P, int precision, const void *theta, void *coef, CoefK ck,
                        hipStream_t s) {
   const dim3 grid = node_grid(g), block(BX, BY, 1);
   if (precision == ETM_PREC_FP64)
-    hipLaunchKernelGGL((coef_kernel<double>), grid, block, 0, s, g, P, (const double *)theta, (double *)coef);
+    hipLaunchKernelGGL((coef_kernel<double>), grid, block, 0, s, g, P, (const double *)theta, (double *)coef, CoefK{});
   else
-    hipLaunchKernelGGL((coef_kernel<float>), grid, block, 0, s, g, P, (const float *)theta, (float *)coef);
+    hipLaunchKernelGGL((coef_kernel<float>), grid, block, 0, s, g, P, (const float *)theta, (float *)coef, ck);
   return hipGetLastError();
 }
 
@@ -836,10 +934,10 @@ hipError_t launch_diag(const DiagLaunch &L, hipStream_t s) {
   const dim3 grid = node_grid(L.g), block(BX, BY, 1);
   const int64_t nb = int64_t(grid.x) * grid.y * grid.z;
   if (L.precision == ETM_PREC_FP64) {
-    hipLaunchKernelGGL((diag_kernel<double, false>), grid, block, 0, s, L);
+    hipLaunchKernelGGL((diag_kernel<double>), grid, block, 0, s, L);
     hipLaunchKernelGGL((diag_finalize<double>), dim3(1), dim3(256), 0, s, L, nb);
   } else {
-    hipLaunchKernelGGL((diag_kernel<float, true>), grid, block, 0, s, L);
+    hipLaunchKernelGGL((diag_kernel<float>), grid, block, 0, s, L);
     hipLaunchKernelGGL((diag_finalize<float>), dim3(1), dim3(256), 0, s, L, nb);
   }
   return hipGetLastError();

@@ -92,10 +92,11 @@ struct EmLaunch {
   int kchunk;             // z planes per block (0 = automatic)
   int pad0;
   double c2dt2;           // (c0 dt)^2
+  double cdt;             // c0 dt (leapfrog form)
   double jf;              // eps0 / dt: Joule factor on e^2 * L * sigma_s-area sums
   int64_t step;           // n of the step being made (e^{n} -> e^{n+1})
   // FP64: e0 = e^n, e1 = e^{n-1}, out = e^{n+1}
-  // MIXED: e0 = e^n (float), e1 = delta^{n-1/2}, out0 / out1 = e^{n+1}, delta^{n+1/2}
+  // MIXED: e0 = e^n (float), e1 = h^{n-1/2} (faces), out0 / out1 = e^{n+1}, h^{n+1/2}
   const void *e0[3];
   const void *e1[3];
   void *out0[3];
@@ -104,6 +105,8 @@ struct EmLaunch {
   const float *theta32;   // FP32 copy (mixed path)
   double *psum;
   const void *coef;       // per node, 6 components at stride cs (see launch_coef)
+  const float *K;         // MIXED: per-edge correction for sigma changes (null when sigma never changes)
+  int8_t *elo;            // MIXED: 8-bit residual of e below its FP32 value (updated in place)
 };
 hipError_t launch_em_step(const EmLaunch &L, hipStream_t s);
 // Refresh the per-node coefficients of the own x, y, z edges for the current
@@ -112,7 +115,13 @@ hipError_t launch_em_step(const EmLaunch &L, hipStream_t s);
 //   mixed: [1/(eps_r + a) x, y, z, 2a x, y, z]
 // with a = dt sigma(T) / (2 eps0) of the materials (port conductances are
 // added in the march); also the eps_r of every port edge.
-hipError_t launch_coef(const DevGrid &g, const DevPorts &P, int precision, const void *theta, void *coef,
+// Mixed path: with K set, also K += (a_new - a_old) (e_cur + e_prev) on every
+// edge whose a changes (e_cur = e^n, e_prev = e^{n-1}; components at stride cs).
+struct CoefK {
+  float *K = nullptr;
+  const float *e_cur = nullptr, *e_prev = nullptr;
+};
+hipError_t launch_coef(const DevGrid &g, const DevPorts &P, int precision, const void *theta, void *coef, CoefK ck,
                        hipStream_t s);
 void em_tiles(const DevGrid &g, int kchunk, int *ntx, int *nty, int *nkc);
 int em_kchunk(const DevGrid &g);
@@ -122,7 +131,7 @@ int em_kchunk(const DevGrid &g);
 struct BatchVar {
   EmLaunch L;             // grid, ports, constants and psum (field pointers unused)
   const void *e[3][3];    // FP64: three rotating e buffers; MIXED: sets 0..1
-  const void *d[2][3];    // MIXED: delta sets
+  const void *h[2][3];    // MIXED: face-field sets
   const double *theta[2];
   const float *theta32;
   int64_t step0;          // plan step at the start of the advance call
@@ -157,7 +166,7 @@ struct DiagLaunch {
   int precision;
   double c2dt2, dt;
   const void *e_new[3];   // e^{n+1}
-  const void *e_old[3];   // FP64: e^n; MIXED: delta^{n+1/2}
+  const void *e_old[3];   // e^n
   const double *theta;
   const double *psum;
   double *partials;
@@ -221,7 +230,7 @@ hipError_t launch_cg_apply_alpha(const MechGrid &M, const CgVecs<T> &v, double *
 // stencils; the smoother is Chebyshev on nodal-block-Jacobi, and the
 // coarsest level is solved with a dense inverse.
 constexpr int kMgMaxLevels = 16;
-constexpr int kMgDeg = 2;   // Chebyshev steps before and after the coarse correction
+constexpr int kMgDeg = 4;   // most Chebyshev steps before (and after) the coarse correction
 constexpr int kMgUpper = 14;  // stored stencil blocks: the centre and the 13 offsets after it
 
 template <typename T>
@@ -244,6 +253,7 @@ struct MgLevel {
   uint8_t *dead;           // per node: bit c = DOF c outside the space (fixed, or no stiffness)
   V3<T> xa, xb, d, b;      // smoother iterates, Chebyshev direction, right-hand side (coarse levels)
   MgAxis ax[3];            // interpolation from level + 1 (unused on the coarsest level)
+  int deg;                 // Chebyshev steps on this level (1..kMgDeg)
   double c1[kMgDeg], c2[kMgDeg];
 };
 

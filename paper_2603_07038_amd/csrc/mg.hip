@@ -827,7 +827,7 @@ hipError_t vcycle_level(const MgDev<T> &G, int l, V3<T> b, const DevScalars *sc,
   }
   V3<T> xc = L.xa, xo = L.xb;
   if (!first_done && (e = smooth(G, l, b, xo, xc, 0, 1, sc, s)) != hipSuccess) return e;
-  for (int k = 1; k < kMgDeg; ++k) {
+  for (int k = 1; k < L.deg; ++k) {
     if ((e = smooth(G, l, b, xc, xo, k, 0, sc, s)) != hipSuccess) return e;
     std::swap(xc, xo);
   }
@@ -843,7 +843,7 @@ hipError_t vcycle_level(const MgDev<T> &G, int l, V3<T> b, const DevScalars *sc,
   V3<T> xcoarse;
   if ((e = vcycle_level(G, l + 1, C.b, sc, &xcoarse, s, fuse != 0)) != hipSuccess) return e;
   hipLaunchKernelGGL((mg_prolong_kernel<T>), lgrid(L), dim3(BX, BY), 0, s, L, xc, C, xcoarse, sc);
-  for (int k = 0; k < kMgDeg; ++k) {
+  for (int k = 0; k < L.deg; ++k) {
     if ((e = smooth(G, l, b, xc, xo, k, 0, sc, s)) != hipSuccess) return e;
     std::swap(xc, xo);
   }

@@ -99,6 +99,11 @@ etm_status validate_and_copy(etm_plan *p, const etm_mesh *mesh, const etm_materi
   if (opts->mg_coarse_dofs == 0) p->opts.mg_coarse_dofs = 800;
   if (p->opts.mg_coarse_dofs < 3 || p->opts.mg_coarse_dofs > 4000)
     return fail(ETM_E_INVAL, "mg_coarse_dofs must be 0 (default) or 3..4000");
+  for (int q = 0; q < 2; ++q) {
+    if (opts->mg_degree[q] == 0) p->opts.mg_degree[q] = 2;
+    if (p->opts.mg_degree[q] < 1 || p->opts.mg_degree[q] > kMgDeg)
+      return fail(ETM_E_INVAL, "mg_degree entries must be 0 (default) or 1..4");
+  }
   p->prec = opts->precision;
   p->R = opts->em_per_thermal;
   // time step
@@ -168,6 +173,7 @@ void mg_levels(etm_plan *p) {
     for (double h : *d[a]) xs[a].push_back(xs[a].back() + h);
   }
   MgHostLevel L0;
+  L0.deg = p->opts.mg_degree[0];
   L0.nx = p->nx; L0.ny = p->ny; L0.nz = p->nz;
   L0.sy = p->sy; L0.sz = p->sz; L0.n = p->ntot;
   p->mg.push_back(L0);
@@ -197,6 +203,7 @@ void mg_levels(etm_plan *p) {
     }
     if (identity) break;
     MgHostLevel C;
+    C.deg = p->opts.mg_degree[1];
     C.nx = cells[0]; C.ny = cells[1]; C.nz = cells[2];
     C.sy = C.nx + 1; C.sz = C.sy * (C.ny + 1); C.n = C.sz * (C.nz + 1);
     p->mg.push_back(C);
@@ -403,7 +410,9 @@ etm_status derive(etm_plan *p, const etm_source *src) {
     for (int b = 0; b < 3; ++b) for (int c = 0; c < 3; ++c) take(p->r_e[b][c], N * 8);
   } else {
     for (int b = 0; b < 2; ++b) for (int c = 0; c < 3; ++c) take(p->r_e[b][c], N * 4);
-    for (int b = 0; b < 2; ++b) for (int c = 0; c < 3; ++c) take(p->r_d[b][c], N * 4);
+    for (int b = 0; b < 2; ++b) for (int c = 0; c < 3; ++c) take(p->r_h[b][c], N * 4);
+    for (int c = 0; c < 3; ++c) take(p->r_K[c], N * 4);
+    take(p->r_elo, 3 * align256(N * 4) / 4);
     take(p->r_theta32, N * 4);
   }
   take(p->r_theta[0], N * 8);
@@ -459,7 +468,10 @@ etm_status derive(etm_plan *p, const etm_source *src) {
     if (p->prec == ETM_PREC_MIXED)
       for (int b = 0; b < 2; ++b)
         for (int c = 1; c < 3; ++c)
-          if (p->r_d[b][c].off - p->r_d[b][c - 1].off != size_t(p->comp_stride) * esz) return fail(ETM_E_INVAL, "layout");
+          if (p->r_h[b][c].off - p->r_h[b][c - 1].off != size_t(p->comp_stride) * esz) return fail(ETM_E_INVAL, "layout");
+    if (p->prec == ETM_PREC_MIXED)
+      for (int c = 1; c < 3; ++c)
+        if (p->r_K[c].off - p->r_K[c - 1].off != size_t(p->comp_stride) * esz) return fail(ETM_E_INVAL, "layout");
     for (int c = 1; c < 6; ++c)
       if (p->r_coef[c].off - p->r_coef[c - 1].off != size_t(p->comp_stride) * esz) return fail(ETM_E_INVAL, "layout");
     if (p->ntot + 2 * p->comp_stride >= (int64_t(1) << 32))
@@ -491,7 +503,7 @@ const void *field_ptr(const etm_plan *p, int field, int *is_f32) {
       *is_f32 = mixed;
       return p->ws + p->r_e[p->cur][field - ETM_FIELD_EX].off;
     case ETM_FIELD_EX_PREV: case ETM_FIELD_EY_PREV: case ETM_FIELD_EZ_PREV:
-      if (mixed) { *is_f32 = 1; return p->ws + p->r_d[p->cur][field - ETM_FIELD_EX_PREV].off; }
+      if (mixed) { *is_f32 = 1; return p->ws + p->r_e[1 - p->cur][field - ETM_FIELD_EX_PREV].off; }
       return p->ws + p->r_e[(p->cur + 2) % 3][field - ETM_FIELD_EX_PREV].off;
     case ETM_FIELD_THETA: return p->ws + p->r_theta[p->th_cur].off;
     case ETM_FIELD_PSUM: return p->ws + p->r_psum.off;
@@ -520,9 +532,9 @@ static void em_pointers(const etm_plan *p, EmLaunch &L) {
     const int s = p->cur, o = 1 - s;
     for (int d = 0; d < 3; ++d) {
       L.e0[d] = p->ws + p->r_e[s][d].off;
-      L.e1[d] = p->ws + p->r_d[s][d].off;
+      L.e1[d] = p->ws + p->r_h[s][d].off;
       L.out0[d] = p->ws + p->r_e[o][d].off;
-      L.out1[d] = p->ws + p->r_d[o][d].off;
+      L.out1[d] = p->ws + p->r_h[o][d].off;
     }
   }
 }
@@ -535,6 +547,7 @@ EmLaunch em_launch_template(const etm_plan *p) {
   L.precision = p->prec;
   L.kchunk = p->kchunk;
   L.c2dt2 = (kC0 * p->dt) * (kC0 * p->dt);
+  L.cdt = kC0 * p->dt;
   L.jf = kEps0 / p->dt;
   L.step = p->step;
   L.theta = p->ptr<double>(p->r_theta[p->th_cur]);
@@ -542,16 +555,27 @@ EmLaunch em_launch_template(const etm_plan *p) {
   L.psum = p->ptr<double>(p->r_psum);
   L.g.cs = uint32_t(p->comp_stride);
   L.coef = p->ws + p->r_coef[0].off;
+  L.K = (p->prec == ETM_PREC_MIXED && p->has_tcr) ? p->ptr<float>(p->r_K[0]) : nullptr;
+  L.elo = p->prec == ETM_PREC_MIXED ? p->ptr<int8_t>(p->r_elo) : nullptr;
   return L;
 }
 
-// Edge coefficients for the current temperature.
-etm_status coef_refresh(etm_plan *p) {
+// Edge coefficients for the current temperature.  With update_k (the
+// temperature changed between two EM steps of a running march) the mixed
+// path also books the change of a into its leapfrog correction K; at bind and
+// restore the coefficients are only (re)computed.
+etm_status coef_refresh(etm_plan *p, bool update_k) {
   DevGrid g = p->dev_grid();
   g.cs = uint32_t(p->comp_stride);
   const void *th = p->prec == ETM_PREC_MIXED ? (const void *)p->ptr<float>(p->r_theta32)
                                              : (const void *)p->ptr<double>(p->r_theta[p->th_cur]);
-  HIP_TRY(launch_coef(g, p->dev_ports(), p->prec, th, p->ws + p->r_coef[0].off, p->stream));
+  CoefK ck;
+  if (update_k && p->prec == ETM_PREC_MIXED) {
+    ck.K = p->ptr<float>(p->r_K[0]);
+    ck.e_cur = p->ptr<float>(p->r_e[p->cur][0]);
+    ck.e_prev = p->ptr<float>(p->r_e[1 - p->cur][0]);
+  }
+  HIP_TRY(launch_coef(g, p->dev_ports(), p->prec, th, p->ws + p->r_coef[0].off, ck, p->stream));
   return ETM_OK;
 }
 
@@ -597,8 +621,7 @@ etm_status diag_record(etm_plan *p, int old_cur) {
   D.dt = p->dt;
   for (int d = 0; d < 3; ++d) {
     D.e_new[d] = p->ws + p->r_e[p->cur][d].off;
-    D.e_old[d] = p->prec == ETM_PREC_FP64 ? (const void *)(p->ws + p->r_e[old_cur][d].off)
-                                          : (const void *)(p->ws + p->r_d[p->cur][d].off);
+    D.e_old[d] = p->ws + p->r_e[old_cur][d].off;
   }
   D.theta = p->ptr<double>(p->r_theta[p->th_cur]);
   D.psum = p->ptr<double>(p->r_psum);
@@ -636,7 +659,7 @@ etm_status thermal_one(etm_plan *p) {
   p->th_cur = 1 - p->th_cur;
   p->n_thermal++;
   p->joule_pending = false;
-  if (p->has_tcr) return coef_refresh(p);
+  if (p->has_tcr) return coef_refresh(p, true);
   return ETM_OK;
 }
 
@@ -715,6 +738,7 @@ MgDev<T> mg_dev(const etm_plan *p) {
       L.ax[a].w = reinterpret_cast<const double *>(tb + H.tab[a][1]);
       L.ax[a].cpos = reinterpret_cast<const int32_t *>(tb + H.tab[a][2]);
     }
+    L.deg = H.deg;
     for (int k = 0; k < kMgDeg; ++k) { L.c1[k] = H.c1[k]; L.c2[k] = H.c2[k]; }
   }
   G.Ainv = p->ptr<T>(p->r_mgainv);
@@ -728,14 +752,14 @@ MgDev<T> mg_dev(const etm_plan *p) {
 // Chebyshev steps for the interval [0.1, 1.1] * lambda_max(Dinv A): the
 // three-term recurrence of Chebyshev acceleration of Richardson iteration,
 // d_0 = r / theta, d_k = c1_k d_{k-1} + c2_k Dinv r_k.
-void cheb_coefs(double lam, double *c1, double *c2) {
+void cheb_coefs(double lam, int deg, double *c1, double *c2) {
   for (int k = 0; k < kMgDeg; ++k) c1[k] = c2[k] = 0.0;
   if (!(lam > 0.0) || !std::isfinite(lam)) return;
   const double hi = 1.1 * lam, lo = 0.1 * lam;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
   double rho = 1.0 / sigma;
   c2[0] = 1.0 / theta;
-  for (int k = 1; k < kMgDeg; ++k) {
+  for (int k = 1; k < deg; ++k) {
     const double rn = 1.0 / (2.0 * sigma - rho);
     c1[k] = rn * rho;
     c2[k] = 2.0 * rn / delta;
@@ -874,7 +898,7 @@ etm_status mg_setup(etm_plan *p) {
     HIP_TRY(hipStreamSynchronize(p->stream));
   }
   p->mg_nlive = int(live.size());
-  for (int l = 0; l + 1 < int(p->mg.size()); ++l) cheb_coefs(lam[l], p->mg[l].c1, p->mg[l].c2);
+  for (int l = 0; l + 1 < int(p->mg.size()); ++l) cheb_coefs(lam[l], p->mg[l].deg, p->mg[l].c1, p->mg[l].c2);
   p->mg_ready = true;
   return ETM_OK;
 }
@@ -1011,6 +1035,7 @@ etm_status etm_opts_default(etm_opts *o) {
   o->cg_rtol = 1e-8;
   o->mech_precond = ETM_PRECOND_MG;
   o->mg_coarse_dofs = 800;
+  o->mg_degree[0] = o->mg_degree[1] = 2;
   return ETM_OK;
 }
 
@@ -1096,7 +1121,7 @@ etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
       (st = up(p->r_mgtab, p->mg_tab.data(), p->mg_tab.size())))
     return st;
   p->bound = true;
-  if ((st = coef_refresh(p)) != ETM_OK) return st;
+  if ((st = coef_refresh(p, false)) != ETM_OK) return st;
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->step = 0; p->cur = 0; p->th_cur = 0; p->rec = 0; p->n_thermal = 0;
   p->n_solves = 0; p->cg_iters = 0; p->cg_outer = 0; p->cg_total = 0; p->cg_relres = 0;
@@ -1167,8 +1192,6 @@ etm_status etm_read(const etm_plan *p, int32_t field, void *dst, size_t bytes, i
   const FieldDesc fd = field_shape(p, field);
   const size_t need = size_t(fd.ni) * fd.nj * fd.nk * 8;
   if (bytes != need) return fail(ETM_E_INVAL, "dst size " + std::to_string(bytes) + " != " + std::to_string(need));
-  const bool mixed_prev = p->prec == ETM_PREC_MIXED && field >= ETM_FIELD_EX_PREV && field <= ETM_FIELD_EZ_PREV;
-  if (mixed_prev && dst_is_device) return fail(ETM_E_INVAL, "e^{n-1} of the mixed path is read to host memory only");
   int f32 = 0;
   const void *src = field_ptr(p, field, &f32);
   double *stage = p->ptr<double>(p->r_stage);
@@ -1176,15 +1199,6 @@ etm_status etm_read(const etm_plan *p, int32_t field, void *dst, size_t bytes, i
   if (!dst_is_device) {
     HIP_TRY(hipMemcpyAsync(dst, stage, need, hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
-    if (mixed_prev) {  // e^{n-1} = e^n - delta^{n-1/2}
-      std::vector<double> e(need / 8);
-      const void *esrc = field_ptr(p, field - ETM_FIELD_EX_PREV, &f32);
-      HIP_TRY(launch_pack(esrc, f32, p->sy, p->sz, fd.ni, fd.nj, fd.nk, stage, p->stream));
-      HIP_TRY(hipMemcpyAsync(e.data(), stage, need, hipMemcpyDeviceToHost, p->stream));
-      HIP_TRY(hipStreamSynchronize(p->stream));
-      double *d = static_cast<double *>(dst);
-      for (size_t q = 0; q < e.size(); ++q) d[q] = e[q] - d[q];
-    }
   }
   return ETM_OK;
 }
@@ -1194,22 +1208,13 @@ etm_status etm_write(etm_plan *p, int32_t field, const void *src, size_t bytes, 
   if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
   if (field < ETM_FIELD_EX || field > ETM_FIELD_UZ || field == ETM_FIELD_VM)
     return fail(ETM_E_INVAL, "field is not writable");
+  if (p->prec == ETM_PREC_MIXED && field >= ETM_FIELD_EX && field <= ETM_FIELD_EZ_PREV)
+    return fail(ETM_E_INVAL, "the mixed path keeps (e, h) as its state: its e fields are set by etm_restore only");
   const FieldDesc fd = field_shape(p, field);
   const size_t need = size_t(fd.ni) * fd.nj * fd.nk * 8;
   if (bytes != need) return fail(ETM_E_INVAL, "src size mismatch");
   double *stage = p->ptr<double>(p->r_stage);
-  std::vector<double> tmp;
   const void *from = src;
-  const bool mixed_prev = p->prec == ETM_PREC_MIXED && field >= ETM_FIELD_EX_PREV && field <= ETM_FIELD_EZ_PREV;
-  if (mixed_prev) {  // store delta^{n-1/2} = e^n - e^{n-1}
-    if (src_is_device) return fail(ETM_E_INVAL, "e^{n-1} of the mixed path is written from host memory only");
-    tmp.resize(need / 8);
-    etm_status st = etm_read(p, field - ETM_FIELD_EX_PREV, tmp.data(), need, 0);
-    if (st != ETM_OK) return st;
-    const double *s = static_cast<const double *>(src);
-    for (size_t q = 0; q < tmp.size(); ++q) tmp[q] -= s[q];
-    from = tmp.data();
-  }
   if (src_is_device) {
     HIP_TRY(hipMemcpyAsync(stage, from, need, hipMemcpyDeviceToDevice, p->stream));
   } else {
@@ -1221,7 +1226,7 @@ etm_status etm_write(etm_plan *p, int32_t field, const void *src, size_t bytes, 
   if (field == ETM_FIELD_THETA && p->prec == ETM_PREC_MIXED)
     HIP_TRY(launch_unpack(stage, fd.ni, fd.nj, fd.nk, p->ptr<float>(p->r_theta32), 1, p->sy, p->sz, p->stream));
   if (field == ETM_FIELD_THETA && p->has_tcr) {
-    etm_status st = coef_refresh(p);
+    etm_status st = coef_refresh(p, true);
     if (st != ETM_OK) return st;
   }
   if (field >= ETM_FIELD_UX && field <= ETM_FIELD_UZ) {
@@ -1260,7 +1265,9 @@ std::vector<const Region *> state_regions(const etm_plan *p) {
   std::vector<const Region *> r;
   for (int b = 0; b < 3; ++b) for (int c = 0; c < 3; ++c) if (p->r_e[b][c].bytes) r.push_back(&p->r_e[b][c]);
   if (p->prec == ETM_PREC_MIXED) {
-    for (int b = 0; b < 2; ++b) for (int c = 0; c < 3; ++c) r.push_back(&p->r_d[b][c]);
+    for (int b = 0; b < 2; ++b) for (int c = 0; c < 3; ++c) r.push_back(&p->r_h[b][c]);
+    for (int c = 0; c < 3; ++c) r.push_back(&p->r_K[c]);
+    r.push_back(&p->r_elo);
     r.push_back(&p->r_theta32);
   }
   r.push_back(&p->r_theta[0]);
@@ -1321,7 +1328,7 @@ etm_status etm_restore(etm_plan *p, const void *src, size_t bytes) {
   p->sol_t[0] = h.sol_t[0]; p->sol_t[1] = h.sol_t[1];
   p->host_status = ETM_OK;
   p->joule_pending = false;
-  return coef_refresh(p);
+  return coef_refresh(p, false);
 }
 
 void etm_plan_destroy(etm_plan *p) {

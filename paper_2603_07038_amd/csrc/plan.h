@@ -31,6 +31,7 @@ struct MgHostLevel {
   int64_t sy = 0, sz = 0, n = 0;       // node strides, entries per vector component
   Region A, Dinv, dead, xa, xb, d, b;  // device regions (A: coarse levels only)
   size_t tab[3][3] = {};               // offsets in r_mgtab of lo, w, cpos per axis (from level + 1)
+  int deg = 2;
   double c1[kMgDeg] = {}, c2[kMgDeg] = {};
 };
 
@@ -65,7 +66,9 @@ struct etm_plan {
   Region r_geo, r_mtab, r_mat, r_flags, r_fixed, r_pkey, r_pgs, r_pstart, r_pwave, r_pwt, r_J, r_probes, r_per;
   Region r_coef[6];     // per-node edge coefficients: eps_r x/y/z, a x/y/z (field precision)
   Region r_e[3][3];     // FP64: three rotating e buffers;  MIXED: [0..1] e sets, [2] unused
-  Region r_d[2][3];     // MIXED: delta sets
+  Region r_h[2][3];     // MIXED: face-field sets h^{n-1/2} (x-, y-, z-normal faces)
+  Region r_K[3];        // MIXED: per-edge correction of the leapfrog form for sigma changes
+  Region r_elo;         // MIXED: 8-bit residual of e (3 components at stride comp_stride)
   Region r_theta[2], r_theta32, r_psum, r_part, r_sc, r_hist;
   Region r_u64[3], r_f64[3], r_r64[3], r_p64[3], r_w64[3], r_dinv64[3], r_uprev64[3];
   Region r_u32[3], r_r32[3], r_p32[3], r_w32[3], r_dinv32[3], r_rhs32[3];
@@ -152,7 +155,7 @@ EmLaunch em_launch_template(const etm_plan *p);
 etm_status em_one_step(etm_plan *p);
 etm_status thermal_one(etm_plan *p);
 etm_status joule_flush(etm_plan *p);
-etm_status coef_refresh(etm_plan *p);
+etm_status coef_refresh(etm_plan *p, bool update_k);
 etm_status diag_record(etm_plan *p, int old_cur);
 etm_status mech_solve_impl(etm_plan *p);
 }  // namespace etm

@@ -7,10 +7,14 @@ HIP graphs).  At every chunk boundary it
 
   * admits queued requests, first come first served, while a batch slot is
     free and the summed device footprint stays within the HBM budget;
-  * retires variants whose EM + thermal march is complete: the mechanical
-    solve (Eq. 8 by Jacobi-PCG) and von Mises (Eq. 9) run on the variant's
-    own state, the results are read back, the workspace is released and the
-    request's latency (arrival -> result on the host) is recorded.
+  * advances every admitted variant by one chunk (or by the fewest steps any
+    of them still needs, so each stops exactly at its own step count);
+  * retires variants whose EM + thermal march is complete: the variant
+    leaves the batch and a worker thread runs its mechanical solve (Eq. 8,
+    multigrid-preconditioned CG) and von Mises stress (Eq. 9) on the
+    variant's own stream, overlapping with the batched march of the others,
+    then reads the results back; the workspace is released and the request's
+    latency (arrival -> result on the host) is recorded.
 
 A variant's results do not depend on what it shares the GPU with: the
 batched EM step runs the same per-node arithmetic as a solo run.
@@ -19,6 +23,8 @@ from __future__ import annotations
 
 import dataclasses
 import time
+from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor
+from concurrent.futures import wait as wait_futures
 from typing import List, Optional
 
 import numpy as np
@@ -56,7 +62,8 @@ class Result:
 
 class Server:
     def __init__(self, max_slots: int = 16, hbm_budget: float = 64e9, precision: int = ETM_PREC_MIXED,
-                 chunk: int = 256, keep_fields: bool = False, tune_json: Optional[str] = None):
+                 chunk: int = 256, keep_fields: bool = False, tune_json: Optional[str] = None,
+                 solve_workers: int = 4):
         import torch
         self.torch = torch
         self.max_slots = max_slots
@@ -68,14 +75,15 @@ class Server:
         self.stream = torch.cuda.Stream()
         self.used = 0.0
         self.active = {}   # slot -> [request, plan, admitted time, EM steps enqueued]
+        self.solving = []  # [future, request, plan, admitted time]
+        self.pool = ThreadPoolExecutor(max_workers=max(1, int(solve_workers)))
+        self._t0 = time.perf_counter()
         self.log: List[str] = []
 
     def _make_plan(self, req: Request):
         p = req.prob
         dt = cfl_dt(p)
         J = p.sample_J_half(dt, p.n_em_steps)
-        if p.n_em_steps % self.chunk:
-            raise ValueError(f"request {req.rid}: {p.n_em_steps} EM steps is not a multiple of the chunk {self.chunk}")
         plan = Plan(p, J, dt=dt, precision=self.precision, n_steps=p.n_em_steps, history=False, bind=False)
         return plan
 
@@ -85,29 +93,49 @@ class Server:
         if len(self.active) >= self.max_slots or self.used + plan.footprint > self.hbm_budget:
             return False
         torch = self.torch
-        with torch.cuda.stream(self.stream):
+        stream = torch.cuda.Stream()   # the variant's own stream (its solve runs there)
+        with torch.cuda.stream(stream):
             ws = torch.empty(plan.footprint + 256, dtype=torch.uint8, device="cuda")
-            plan.bind(ws, self.stream)
+            plan.bind(ws, stream)
         slot = self.batch.attach(plan)
         self.active[slot] = [req, plan, now, 0]
+        self.log.append(f"admit {req.rid} slot {slot} stream {stream.cuda_stream:#x} at {now:.3f}")
         self.used += plan.footprint
         return True
 
-    def _retire(self, slot: int, now_fn) -> Result:
-        req, plan, admitted, _ = self.active.pop(slot)
-        self.batch.detach(slot)
+    def _finish(self, plan):
+        """Worker thread: solve, von Mises, read back; returns (info, theta, vm, time)."""
         plan.mech_solve()
         info = plan.sync()
         theta = plan.read(ETM_FIELD_THETA)
         vm = plan.read(ETM_FIELD_VM)
-        res = Result(rid=req.rid, name=req.prob.name, cells=req.prob.n_cells, em_steps=req.prob.n_em_steps,
-                     arrival=req.arrival, admitted=admitted, finished=now_fn(), theta_max=float(theta.max()),
-                     vm_max=float(vm.max()), cg_iters=int(info["cg_iters"]), cg_relres=float(info["cg_relres"]),
-                     theta=theta if self.keep_fields else None, vm=vm if self.keep_fields else None)
-        self.used -= plan.footprint
-        plan.ws = None
-        del plan
-        return res
+        return info, theta, vm, time.perf_counter() - self._t0
+
+    def _retire(self, slot: int):
+        req, plan, admitted, _ = self.active.pop(slot)
+        self.batch.detach(slot)
+        self.log.append(f"retire {req.rid} slot {slot}")
+        self.solving.append([self.pool.submit(self._finish, plan), req, plan, admitted])
+
+    def _collect(self, done: List[Result], block: float = 0.0):
+        if not self.solving:
+            return
+        if block > 0.0:
+            wait_futures([e[0] for e in self.solving], timeout=block, return_when=FIRST_COMPLETED)
+        keep = []
+        for fut, req, plan, admitted in self.solving:
+            if not fut.done():
+                keep.append([fut, req, plan, admitted])
+                continue
+            info, theta, vm, finished = fut.result()
+            done.append(Result(rid=req.rid, name=req.prob.name, cells=req.prob.n_cells, em_steps=req.prob.n_em_steps,
+                               arrival=req.arrival, admitted=admitted, finished=finished,
+                               theta_max=float(theta.max()), vm_max=float(vm.max()), cg_iters=int(info["cg_iters"]),
+                               cg_relres=float(info["cg_relres"]), theta=theta if self.keep_fields else None,
+                               vm=vm if self.keep_fields else None))
+            self.used -= plan.footprint
+            plan.ws = None
+        self.solving = keep
 
     def run(self, requests: List[Request], realtime: bool = True) -> List[Result]:
         """Serve all requests; arrivals are honoured in wall-clock time when
@@ -115,27 +143,34 @@ class Server:
         pending = sorted(requests, key=lambda r: r.arrival)
         queue: List = []
         done: List[Result] = []
-        t0 = time.perf_counter()
+        self._t0 = t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
-        while pending or queue or self.active:
+        while pending or queue or self.active or self.solving:
             t = now()
             while pending and (not realtime or pending[0].arrival <= t):
                 r = pending.pop(0)
                 queue.append((r, self._make_plan(r)))
+            self._collect(done)
             while queue:
                 r, plan = queue[0]
                 if not self._admit(r, plan, now()):
                     break
                 queue.pop(0)
             if not self.active:
-                if pending and realtime:
-                    time.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
+                # nothing to march: wait for a solve to finish or the next arrival
+                nxt = max(0.0, pending[0].arrival - now()) if (pending and realtime) else 0.05
+                if self.solving:
+                    self._collect(done, block=min(max(nxt, 1e-3), 0.05))
+                elif pending and realtime:
+                    time.sleep(min(nxt, 0.05))
                 continue
-            self.batch.advance(self.chunk, self.stream)
+            n = min([self.chunk] + [ent[0].prob.n_em_steps - ent[3] for ent in self.active.values()])
+            if n > 0:
+                self.batch.advance(n, self.stream)
             for ent in self.active.values():
-                ent[3] += self.chunk
+                ent[3] += n
             for slot in [s for s, ent in self.active.items() if ent[3] >= ent[0].prob.n_em_steps]:
-                done.append(self._retire(slot, now))
+                self._retire(slot)
         return done
 
 

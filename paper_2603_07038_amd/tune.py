@@ -1,0 +1,92 @@
+"""Autotuner for the batched EM march: the z-chunk (tile height) per size class.
+
+    python -m paper_2603_07038_amd.tune [--out FILE] [--classes 15-24] [--steps 64]
+
+The batched march works on 64x4-node column tiles cut into z-chunks of
+``kchunk`` node planes.  Short chunks give more work items (better load
+balance when few variants are attached) but stage two extra planes per
+chunk; long chunks amortise the halo.  For each size class (floor of log2 of
+the cell count, the key the batch uses) a package variant of that size is
+replicated until the batch holds at least 16 M cells, and every candidate
+chunk is timed over graph-replayed EM steps.  The fastest per class is
+written as ``{"kchunk": {"<class>": k, ...}, "timings_us": {...}}``, the
+table ``Batch`` reads (``tune_gfx950.json`` next to this file by default).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "tune_gfx950.json")
+CANDIDATES = (2, 4, 8, 16, 32, 64)
+
+
+def class_problem(c: int):
+    """A package variant with about 2**c cells (1 um voxels)."""
+    import workloads as W
+    nz = 32 if c <= 18 else (48 if c <= 21 else 64)
+    n = max(8, int(round(math.sqrt(2.0 ** (c + 0.5) / nz))))
+    return W.package(n, n, nz, 9000 + c, bump_pitch_um=20.0, bump_cells=6, trace_width=3, trace_pitch=6,
+                     n_trace_layers=4, max_traces=16, n_bits=64, steps_per_bit=4, em_per_thermal=1024,
+                     name=f"tune{c}")
+
+
+def time_class(c: int, steps: int, precision: int):
+    import torch
+    from . import Batch, Plan, cfl_dt
+    p = class_problem(c)
+    assert int(math.floor(math.log2(p.n_cells))) == c, (c, p.n_cells)
+    copies = max(1, min(32, (16 << 20) // p.n_cells))
+    dt = cfl_dt(p)
+    J = p.sample_J_half(dt, 4 * steps)
+    res = {}
+    for kc in CANDIDATES:
+        if kc > p.nz + 1 and kc != CANDIDATES[0]:
+            continue
+        b = Batch(copies + 1, json.dumps({"kchunk": {str(c): kc}}))
+        plans = [Plan(p, J, dt=dt, precision=precision, n_steps=4 * steps, history=False) for _ in range(copies)]
+        for pl in plans:
+            b.attach(pl)
+        s = torch.cuda.Stream()
+        b.advance(steps, s)  # warm-up: captures the graph of this segment length
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        b.advance(steps, s)
+        e1.record(s)
+        e1.synchronize()
+        res[kc] = e0.elapsed_time(e1) * 1e3 / steps
+        del b, plans
+        torch.cuda.synchronize()
+    return res, copies, p.n_cells
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--classes", default="15-24")
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    a = ap.parse_args(argv)
+    from . import ETM_PREC_FP64, ETM_PREC_MIXED
+    prec = ETM_PREC_MIXED if a.precision == "mixed" else ETM_PREC_FP64
+    lo, hi = (int(x) for x in a.classes.split("-"))
+    table = {"kchunk": {}, "timings_us": {}, "precision": a.precision, "candidates": list(CANDIDATES)}
+    for c in range(lo, hi + 1):
+        res, copies, cells = time_class(c, a.steps, prec)
+        best = min(res, key=res.get)
+        table["kchunk"][str(c)] = best
+        table["timings_us"][str(c)] = {str(k): round(v, 2) for k, v in res.items()}
+        print(json.dumps({"class": c, "cells": cells, "copies": copies, "best": best,
+                          "us_per_step": {k: round(v, 1) for k, v in res.items()}}), flush=True)
+    with open(a.out, "w") as f:
+        json.dump(table, f, indent=1)
+    print("wrote", a.out)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(HERE))
+    main()

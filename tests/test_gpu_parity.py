@@ -161,3 +161,52 @@ def test_chunked_advance_and_rerun_are_bitwise_equal():
     for x, y in zip(a.e(), b.e()):
         np.testing.assert_array_equal(x, y)
     np.testing.assert_array_equal(a.read(etm.ETM_FIELD_THETA), b.read(etm.ETM_FIELD_THETA))
+
+
+def _mixed_vs_oracle(prob, n_steps):
+    o = oracle.Oracle(prob)
+    dt = o.cfl_dt()
+    J = prob.sample_J_half(dt, n_steps)
+    plan = etm.Plan(prob, J, dt=dt, precision=etm.ETM_PREC_MIXED, n_steps=n_steps, history=False)
+    plan.advance(n_steps)
+    plan.sync()
+    st, _ = o.run(dt, n_steps, J)
+    return plan, st, o
+
+
+def test_mixed_leapfrog_accuracy_on_a_prbs_package():
+    """A PRBS-driven package over 2048 steps (Norton ports, Cu traces and
+    bumps in dielectrics): the FP32 leapfrog state keeps the temperature rise
+    within 1e-6 and the field within 1e-5 of the FP64 oracle."""
+    prob = W.package(40, 40, 24, 77, bump_pitch_um=20, bump_cells=6, trace_width=2, trace_pitch=4,
+                     n_trace_layers=2, max_traces=6, n_bits=128, steps_per_bit=16, em_per_thermal=256)
+    plan, st, o = _mixed_vs_oracle(prob, 2048)
+    th_err = rel_err(plan.read(etm.ETM_FIELD_THETA), st["theta"])
+    ee = e_err(plan.e(), st["e"])
+    _say(f"[parity] prbs package mixed theta err {th_err:.3e} e err {ee:.3e}")
+    assert th_err < 1e-6
+    assert ee < 1e-5
+    # e^{n-1} is the previous field of the march
+    assert e_err(plan.e_prev(), st["e_prev"]) < 1e-5
+
+
+def test_mixed_leapfrog_tracks_sigma_of_T_under_strong_heating():
+    """The trace case driven 300x harder (tens of mK per thermal block, Cu
+    conductivity 3.9e-3/K): the leapfrog correction K keeps the mixed path on
+    the three-level scheme of Eq. (2) with sigma(T^n)."""
+    prob = W.config1()
+    for w in prob.waves:
+        w.amp *= 300.0
+    plan, st, o = _mixed_vs_oracle(prob, prob.n_em_steps)
+    th = st["theta"]
+    th_err = rel_err(plan.read(etm.ETM_FIELD_THETA), th)
+    _say(f"[parity] strong heating theta max {th.max():.3e} K, mixed theta err {th_err:.3e}")
+    assert th.max() > 1e-2
+    assert th_err < 1e-6
+
+
+def test_mixed_e_fields_are_not_writable():
+    prob = W.random_problem(3, 6, 5, 4, n_steps=4, R=2)
+    plan = etm.Plan(prob, prob.sample_J_half(etm.cfl_dt(prob), 4), precision=etm.ETM_PREC_MIXED, n_steps=4)
+    with pytest.raises(etm.EtmError):
+        plan.write(etm.ETM_FIELD_EX, np.zeros(plan.field_shape(etm.ETM_FIELD_EX)))
