@@ -9,22 +9,20 @@
 // with er the edge's mean relative permittivity, a = dt sigma_e / (2 eps0)
 // (port conductances included), C the purely geometric curl-curl
 // (curl mu0^-1 curl = C / mu0) and jd = dt (J^{n+1/2} - J^{n-1/2}) / eps0.
-// The mixed path carries (e, delta = e^{n+1} - e^n) in FP32 and updates
-//   delta^{n+1/2} = delta^{n-1/2} - [2a delta^{n-1/2} + (c0 dt)^2 C e^n + jd] / (er + a),
-//   e^{n+1} = e^n + delta^{n+1/2},
-// which is the same recurrence rearranged so that FP32 rounding is not
-// integrated twice and a lossless edge carries delta forward exactly.
-// Edge coefficients are always formed in FP64 and rounded once.
+// The mixed path marches the same scheme as leapfrog on (e^n, h^{n-1/2}),
+// both stored in FP32 and combined in FP64, with an 8-bit residual that
+// extends the stored e below its FP32 rounding (em_march_tile_yee).  Edge
+// coefficients are always formed in FP64 and rounded once.
 //
-// March kernel.  A block owns a 64 x 4 column of nodes and marches up a
-// chunk of z planes, staging three e planes (k-1, k, k+1) with a one-node
-// halo in LDS, so each e value is fetched from memory once per step.  A node
-// updates the x-, y- and z-edges that start at it.  The Joule source is
-// gathered one step late: the node sums sigma e^2 L A over its six incident
-// edges of the *input* field e^n, which the stencil already holds, so no
-// edge update is recomputed and no atomics are needed.  The power of the
-// last step of a thermal block is added by the thermal kernel (or by a flush
-// kernel at the end of an advance call) before temperature changes.
+// March kernels.  A block owns a 64 x 4 column of nodes and marches up a
+// chunk of z planes, staging e planes with a one-node halo in LDS, so each e
+// value is fetched from memory once per step.  A node updates the x-, y- and
+// z-edges that start at it.  The Joule source is gathered one step late: the
+// node sums sigma e^2 L A over its six incident edges of the *input* field
+// e^n, which the stencil already holds, so no edge update is recomputed.
+// The power of the last step of a thermal block is added by the thermal
+// kernel (or by a flush kernel at the end of an advance call) before
+// temperature changes.
 #include <algorithm>
 
 #include "etm_internal.h"
@@ -218,16 +216,15 @@ __device__ __forceinline__ int find_port(const DevPorts &P, int64_t key) {
   return -1;
 }
 
-// Source and lumped conductance of the port edge (key) at this step.
+// Source and lumped conductance of port edge q (from find_port) at this step.
 // Port source of EM step n at an edge: jd = dt (J^{n+1/2} - J^{n-1/2}) / eps0
 // (three-level form), jn = dt J^{n+1/2} / eps0 (leapfrog form), and the
 // lumped conductance g (scaled like the a-coefficient).
 struct PortTerm {
   double jd, jn, g;
 };
-__device__ __forceinline__ PortTerm port_terms(const DevPorts &P, int64_t key, int64_t step) {
+__device__ __forceinline__ PortTerm port_terms(const DevPorts &P, int q, int64_t step) {
   PortTerm r{0.0, 0.0, 0.0};
-  const int q = find_port(P, key);
   if (q < 0) return r;
   r.g = P.gs[q];
   const int64_t s1 = step + 1, s0 = step, ns = P.n_samples;
@@ -245,14 +242,15 @@ __device__ __forceinline__ PortTerm port_terms(const DevPorts &P, int64_t key, i
 // accumulation e^{n+1} = e^n + (e^{n+1} - e^n) runs on the full value, so
 // the per-step rounding of e (which otherwise dominates the error of the
 // temperature rise over long windows) is 256 times smaller.
-__device__ __forceinline__ double ulp32(float h) {
-  const int E = int((__float_as_uint(h) >> 23) & 0xFFu);
-  return ldexp(1.0, max(E, 1) - 150);
+// log2 of ulp(hi) / 256 (subnormals share the smallest binade's ulp)
+__device__ __forceinline__ int lo_exp(float hi) {
+  const int E = int((__float_as_uint(hi) >> 23) & 0xFFu);
+  return max(E, 1) - 158;
 }
-__device__ __forceinline__ double e_join(float hi, int8_t lo) { return double(hi) + double(lo) * (ulp32(hi) * (1.0 / 256.0)); }
+__device__ __forceinline__ double e_join(float hi, int8_t lo) { return double(hi) + ldexp(double(lo), lo_exp(hi)); }
 __device__ __forceinline__ void e_split(double x, float &hi, int8_t &lo) {
   hi = float(x);
-  const double r = rint((x - double(hi)) / ulp32(hi) * 256.0);
+  const double r = rint(ldexp(x - double(hi), -lo_exp(hi)));  // exact scaling by a power of two
   lo = int8_t(fmax(-128.0, fmin(127.0, r)));
 }
 
@@ -306,23 +304,12 @@ __device__ __forceinline__ double joule_from_coef(const T *cf, uint32_t cs, uint
   return node_joule(a6, ax, ay, az, v, jf);
 }
 
+// ---- FP64: the three-level form of Eq. (2)-(3) on (e^n, e^{n-1}) -----------
 // One block: the 64 x 4 node column (tx, ty) over the z planes of chunk kc.
 // Per plane: stage e plane k+1, update the own edges of the nodes of plane
 // k from their stored coefficients, and gather the Joule power of e^n at the
 // node from its six incident edges.
-// One z-march of a 64 x 4 column tile.  FP64 (YEE = false): the
-// three-level form of Eq. (2)-(3) on (e^n, e^{n-1}).  Mixed (YEE = true): the
-// same scheme written as leapfrog on (e^n, h^{n-1/2}), both stored in FP32
-// and combined in FP64:
-//   h^{n+1/2} = h^{n-1/2} + c0 dt curl e^n                       (faces)
-//   (er + a) (e^{n+1} - e^n) = -2a e^n - c0 dt curl^T h^{n+1/2} - jn + K
-// Eliminating h gives Eq. (2) exactly; K (per edge, zero until sigma changes)
-// carries the difference the three-level form keeps when a changes at a
-// thermal step.  Rounding errors of h reach e only through curl^T, so they
-// never feed the gradient (static-charge) modes the curl-curl leaves
-// undamped in dielectrics; the increment form e^{n+1} - e^n stored in FP32
-// lets them accumulate.
-template <typename T, bool YEE>
+template <typename T>
 __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T> &p, int64_t step, int tx, int ty,
                                               int kc, int kchunk, int acc_joule, MarchSmem<T> &S) {
   const DevGrid &g = L.g;
@@ -356,8 +343,6 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
   const int pec = g.pec;
   const bool pec_i = (i == 0 && (pec & 1)) || (i == nx && (pec & 2));
   const bool pec_j = (j == 0 && (pec & 4)) || (j == ny && (pec & 8));
-  // leapfrog form: the two faces below (k-1) carry over from the previous plane
-  float hy_prev = 0.0f, hx_prev = 0.0f;
   int s_m = 0, s_0 = 1, s_p = 2;
   load_plane(k0 - 1, s_m);
   load_plane(k0, s_0);
@@ -374,119 +359,45 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
       const uint8_t fl = (g.flags[n] & 7);
       const T e0x = E(0, 0, 0, 0), e0y = E(1, 0, 0, 0), e0z = E(2, 0, 0, 0);
       const bool pec_d[3] = {pec_j || pec_k, pec_i || pec_k, pec_i || pec_j};
-      if constexpr (YEE) {
-        const double cdt = L.cdt;
-        const double dxi = G.idx[min(ic, nx - 1)], dxm = G.idx[max(ic - 1, 0)], dhx = G.ihx[ic];
-        const double dyj = G.idy[min(jc, ny - 1)], dym = G.idy[max(jc - 1, 0)], dhy = G.ihy[jc];
-        const double dzk = G.idz[min(k, nz - 1)], dzm = G.idz[max(k - 1, 0)], dhz = G.ihz[k];
-        const float *hi = reinterpret_cast<const float *>(p.aux);
-        float *ho = reinterpret_cast<float *>(p.oaux);
-        // own faces (x-normal hx, y-normal hy, z-normal hz at node n)
-        float hz_c = 0.0f, hy_c = 0.0f, hx_c = 0.0f;
-        if (i < nx && j < ny) hz_c = hface(hi[2 * cs + n], e0x, E(0, 0, 1, 0), dyj, E(1, 1, 0, 0), e0y, dxi, cdt);
-        if (i < nx && k < nz) hy_c = hface(hi[cs + n], e0z, E(2, 1, 0, 0), dxi, E(0, 0, 0, 1), e0x, dzk, cdt);
-        if (j < ny && k < nz) hx_c = hface(hi[n], E(2, 0, 1, 0), e0z, dyj, e0y, E(1, 0, 0, 1), dzk, cdt);
-        if (i < nx && j < ny) ho[2 * cs + n] = hz_c;
-        if (i < nx && k < nz) ho[cs + n] = hy_c;
-        if (j < ny && k < nz) ho[n] = hx_c;
-        // faces below in y and x (another thread's, recomputed identically)
-        float hz_jm = 0.0f, hx_jm = 0.0f, hz_im = 0.0f, hy_im = 0.0f, hy_km = 0.0f, hx_km = 0.0f;
-        if (j > 0 && i < nx)
-          hz_jm = hface(hi[2 * cs + n - sy], E(0, 0, -1, 0), e0x, dym, E(1, 1, -1, 0), E(1, 0, -1, 0), dxi, cdt);
-        if (j > 0 && k < nz)
-          hx_jm = hface(hi[n - sy], e0z, E(2, 0, -1, 0), dym, E(1, 0, -1, 0), E(1, 0, -1, 1), dzk, cdt);
-        if (i > 0 && j < ny)
-          hz_im = hface(hi[2 * cs + n - 1], E(0, -1, 0, 0), E(0, -1, 1, 0), dyj, e0y, E(1, -1, 0, 0), dxm, cdt);
-        if (i > 0 && k < nz)
-          hy_im = hface(hi[cs + n - 1], E(2, -1, 0, 0), e0z, dxm, E(0, -1, 0, 1), E(0, -1, 0, 0), dzk, cdt);
-        if (k > 0) {
-          if (k > k0) {
-            hy_km = hy_prev;
-            hx_km = hx_prev;
-          } else {
-            if (i < nx) hy_km = hface(hi[cs + n - sz], E(2, 0, 0, -1), E(2, 1, 0, -1), dxi, e0x, E(0, 0, 0, -1), dzm, cdt);
-            if (j < ny) hx_km = hface(hi[n - sz], E(2, 0, 1, -1), E(2, 0, 0, -1), dyj, E(1, 0, 0, -1), e0y, dzm, cdt);
-          }
-        }
-        hy_prev = hy_c;
-        hx_prev = hx_c;
-        const float *Kp = L.K;
+      const T idz_k = T(G.idz[min(k, nz - 1)]), idz_m = T(G.idz[max(k - 1, 0)]), ihz_k = T(G.ihz[k]);
+      const T vk0 = T(k > 0), vk1 = T(k < nz);
+      // curl-curl of e^n on the three own edges (faces outside the mesh masked to 0)
+      const T hz_c = (e0x - E(0, 0, 1, 0)) * idy_j + (E(1, 1, 0, 0) - e0y) * idx_i;        // hz(i, j)
+      const T hy_c = (e0z - E(2, 1, 0, 0)) * idx_i + (E(0, 0, 0, 1) - e0x) * idz_k;        // hy(i, k)
+      const T hx_c = (E(2, 0, 1, 0) - e0z) * idy_j - (E(1, 0, 0, 1) - e0y) * idz_k;        // hx(j, k)
 #pragma unroll
-        for (int D = 0; D < 3; ++D) {
-          const bool exists = D == 0 ? i < nx : D == 1 ? j < ny : k < nz;
-          if (!exists) continue;
-          const uint32_t o = D * cs + n;
-          if (pec_d[D]) {
-            p.oe[o] = T(0);
-            L.elo[o] = 0;
-            continue;
-          }
-          double cc;
-          if (D == 0)
-            cc = (double(hz_c) - double(hz_jm)) * dhy - (double(hy_c) - double(hy_km)) * dhz;
-          else if (D == 1)
-            cc = (double(hx_c) - double(hx_km)) * dhz - (double(hz_c) - double(hz_im)) * dhx;
-          else
-            cc = (double(hy_c) - double(hy_im)) * dhx - (double(hx_c) - double(hx_jm)) * dhy;
-          // stored: 1/(er + a) and 2a, each rounded once from FP64
-          double inv = double(cf[D * cs + n]), a2 = double(cf[(3 + D) * cs + n]), jn = 0.0;
-          if (fl & (1 << D)) {
-            const int q = find_port(L.ports, int64_t(D) * g.ntot + n);
-            const PortTerm pt = port_terms(L.ports, int64_t(D) * g.ntot + n, step);
-            const double a = 0.5 * a2 + pt.g;
-            inv = rcp64(L.ports.er[q] + a);
-            a2 = 2.0 * a;
-            jn = pt.jn;
-          }
-          const float e0h = D == 0 ? e0x : D == 1 ? e0y : e0z;
-          const double kk = Kp ? double(Kp[o]) : 0.0;
-          const double dl = -(a2 * double(e0h) + cdt * cc + jn - kk) * inv;
-          float eh;
-          int8_t el;
-          e_split(e_join(e0h, L.elo[o]) + dl, eh, el);
-          p.oe[o] = T(eh);
-          L.elo[o] = el;
+      for (int D = 0; D < 3; ++D) {
+        const bool exists = D == 0 ? i < nx : D == 1 ? j < ny : k < nz;
+        if (!exists) continue;
+        const uint32_t o = D * cs + n;
+        if (pec_d[D]) {
+          p.oe[o] = T(0);
+          continue;
         }
-      } else {
-        const T idz_k = T(G.idz[min(k, nz - 1)]), idz_m = T(G.idz[max(k - 1, 0)]), ihz_k = T(G.ihz[k]);
-        const T vk0 = T(k > 0), vk1 = T(k < nz);
-        // curl-curl of e^n on the three own edges (faces outside the mesh masked to 0)
-        const T hz_c = (e0x - E(0, 0, 1, 0)) * idy_j + (E(1, 1, 0, 0) - e0y) * idx_i;        // hz(i, j)
-        const T hy_c = (e0z - E(2, 1, 0, 0)) * idx_i + (E(0, 0, 0, 1) - e0x) * idz_k;        // hy(i, k)
-        const T hx_c = (E(2, 0, 1, 0) - e0z) * idy_j - (E(1, 0, 0, 1) - e0y) * idz_k;        // hx(j, k)
-#pragma unroll
-        for (int D = 0; D < 3; ++D) {
-          const bool exists = D == 0 ? i < nx : D == 1 ? j < ny : k < nz;
-          if (!exists) continue;
-          const uint32_t o = D * cs + n;
-          if (pec_d[D]) {
-            p.oe[o] = T(0);
-            continue;
-          }
-          T cc;
-          if (D == 0) {
-            const T hz_jm = (E(0, 0, -1, 0) - e0x) * idy_m + (E(1, 1, -1, 0) - E(1, 0, -1, 0)) * idx_i;
-            const T hy_km = (E(2, 0, 0, -1) - E(2, 1, 0, -1)) * idx_i + (e0x - E(0, 0, 0, -1)) * idz_m;
-            cc = (vj1 * hz_c - vj0 * hz_jm) * ihy_j - (vk1 * hy_c - vk0 * hy_km) * ihz_k;
-          } else if (D == 1) {
-            const T hx_km = (E(2, 0, 1, -1) - E(2, 0, 0, -1)) * idy_j - (e0y - E(1, 0, 0, -1)) * idz_m;
-            const T hz_im = (E(0, -1, 0, 0) - E(0, -1, 1, 0)) * idy_j + (e0y - E(1, -1, 0, 0)) * idx_m;
-            cc = (vk1 * hx_c - vk0 * hx_km) * ihz_k - (vi1 * hz_c - vi0 * hz_im) * ihx_i;
-          } else {
-            const T hy_im = (E(2, -1, 0, 0) - e0z) * idx_m + (E(0, -1, 0, 1) - E(0, -1, 0, 0)) * idz_k;
-            const T hx_jm = (e0z - E(2, 0, -1, 0)) * idy_m - (E(1, 0, -1, 1) - E(1, 0, -1, 0)) * idz_k;
-            cc = (vi1 * hy_c - vi0 * hy_im) * ihx_i - (vj1 * hx_c - vj0 * hx_jm) * ihy_j;
-          }
-          const T e0 = D == 0 ? e0x : D == 1 ? e0y : e0z;
-          T er = cf[D * cs + n], a = cf[(3 + D) * cs + n], jd = T(0);
-          if (fl & (1 << D)) {
-            const PortTerm pt = port_terms(L.ports, int64_t(D) * g.ntot + n, step);
-            a = T(double(a) + pt.g);
-            jd = T(pt.jd);
-          }
-          const T inv = T(rcp64(double(er) + double(a)));
-          p.oe[o] = (T(2) * er * e0 - c2 * cc - (er - a) * p.aux[o] - jd) * inv;
+        T cc;
+        if (D == 0) {
+          const T hz_jm = (E(0, 0, -1, 0) - e0x) * idy_m + (E(1, 1, -1, 0) - E(1, 0, -1, 0)) * idx_i;
+          const T hy_km = (E(2, 0, 0, -1) - E(2, 1, 0, -1)) * idx_i + (e0x - E(0, 0, 0, -1)) * idz_m;
+          cc = (vj1 * hz_c - vj0 * hz_jm) * ihy_j - (vk1 * hy_c - vk0 * hy_km) * ihz_k;
+        } else if (D == 1) {
+          const T hx_km = (E(2, 0, 1, -1) - E(2, 0, 0, -1)) * idy_j - (e0y - E(1, 0, 0, -1)) * idz_m;
+          const T hz_im = (E(0, -1, 0, 0) - E(0, -1, 1, 0)) * idy_j + (e0y - E(1, -1, 0, 0)) * idx_m;
+          cc = (vk1 * hx_c - vk0 * hx_km) * ihz_k - (vi1 * hz_c - vi0 * hz_im) * ihx_i;
+        } else {
+          const T hy_im = (E(2, -1, 0, 0) - e0z) * idx_m + (E(0, -1, 0, 1) - E(0, -1, 0, 0)) * idz_k;
+          const T hx_jm = (e0z - E(2, 0, -1, 0)) * idy_m - (E(1, 0, -1, 1) - E(1, 0, -1, 0)) * idz_k;
+          cc = (vi1 * hy_c - vi0 * hy_im) * ihx_i - (vj1 * hx_c - vj0 * hx_jm) * ihy_j;
         }
+        const T e0 = D == 0 ? e0x : D == 1 ? e0y : e0z;
+        T er = cf[D * cs + n], a = cf[(3 + D) * cs + n], jd = T(0);
+        if (fl & (1 << D)) {
+          const int q = find_port(L.ports, int64_t(D) * g.ntot + n);
+          const PortTerm pt = port_terms(L.ports, q, step);
+          a = T(double(a) + pt.g);
+          jd = T(pt.jd);
+        }
+        const T inv = T(rcp64(double(er) + double(a)));
+        p.oe[o] = (T(2) * er * e0 - c2 * cc - (er - a) * p.aux[o] - jd) * inv;
       }
       if (acc_joule) {
         const double az[2] = {G.azl[k], G.azh[k]};
@@ -502,6 +413,292 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
   }
 }
 
+// ---- mixed: the same scheme as leapfrog on (e^n, h^{n-1/2}) ----------------
+// Both fields are stored in FP32 and combined in FP64:
+//   h^{n+1/2} = h^{n-1/2} + c0 dt curl e^n                       (faces)
+//   (er + a) (e^{n+1} - e^n) = -2a e^n - c0 dt curl^T h^{n+1/2} - jn + K
+// Eliminating h gives Eq. (2) exactly; K (per edge, zero until sigma changes)
+// carries the difference the three-level form keeps when a changes at a
+// thermal step.  Rounding errors of h reach e only through curl^T, so they
+// never feed the gradient (static-charge) modes the curl-curl leaves
+// undamped in dielectrics; the increment form e^{n+1} - e^n stored in FP32
+// lets them accumulate.
+//
+// Per z plane a block first forms the h faces of its 64 x 4 nodes (each
+// thread its own three, and 136 threads the faces of the low-side halo
+// row and column that the edge update needs), puts them in LDS, then
+// updates the three own edges of every node.  Every face is computed once
+// per block with one expression, so a face at a tile or chunk border is
+// bitwise the value its owner stores.  A four-plane e ring and two face
+// buffers need two barriers per plane; the next e plane and the next plane's
+// per-node inputs are fetched into registers while the current plane is
+// computed.
+struct YeeSmem {
+  float e[4][3][TYH][TXH];        // e^n (FP32 part), planes k-1 .. k+2 in a ring
+  float f[2][3][BY + 1][BX + 1];  // h^{n+1/2} of plane k: [x-, y-, z-normal][j - j0 + 1][i - i0 + 1]
+};
+constexpr int kHalo = 2 * BX + 2 * BY;  // halo faces: z- and x-normal of row j0-1, z- and y-normal of column i0-1
+
+// Per-node inputs of one plane for the edge update.
+struct YeeNode {
+  float inv[3], a2[3], K[3];
+  float a2xm, a2ym;  // 2a of the x-edge at i-1 and the y-edge at j-1 (Joule)
+  int8_t lo[3];
+  uint8_t fl;
+};
+
+__device__ __forceinline__ void em_march_tile_yee(const EmLaunch &L, const EmPtrs<float> &p, int64_t step, int tx,
+                                                  int ty, int kc, int kchunk, int acc_joule, YeeSmem &S) {
+  const DevGrid &g = L.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const uint32_t sy = uint32_t(g.sy), sz = uint32_t(g.sz), cs = g.cs;
+  const Geo G(g.geo, nx, ny, nz);
+  const float *cf = static_cast<const float *>(L.coef);
+  const float *Kp = L.K;
+  int8_t *elo = L.elo;
+  const double cdt = L.cdt;
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * BX + lx;
+  const int i0 = tx * BX, j0 = ty * BY;
+  const int i = i0 + lx, j = j0 + ly;
+  const int k0 = kc * kchunk, k1 = min(k0 + kchunk, nz + 1);
+  const bool active = i <= nx && j <= ny;
+  const int ic = min(i, nx), jc = min(j, ny);
+  const uint32_t nxy = uint32_t(jc) * sy + uint32_t(ic);  // clamped: every load below is in bounds
+
+  // ---- e plane staging: entries tid and tid + 256 of the TYH x TXH tile
+  constexpr int kTile = TYH * TXH;
+  static_assert(kTile <= 2 * BX * BY, "two staging entries per thread");
+  uint32_t qxy[2];
+  bool okxy[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int t = tid + u * BX * BY;
+    const int r = t / TXH, c = t - r * TXH;
+    const int gi = i0 - 1 + c, gj = j0 - 1 + r;
+    okxy[u] = t < kTile && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny;
+    qxy[u] = okxy[u] ? uint32_t(gj) * sy + uint32_t(gi) : 0u;
+  }
+  auto fetch_plane = [&](int kk, float (&v)[2][3]) {
+    const bool okz = kk >= 0 && kk <= nz;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const bool ok = okz && okxy[u];
+      const uint32_t q = ok ? uint32_t(kk) * sz + qxy[u] : 0u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float x = p.e[c * cs + q];
+        v[u][c] = ok ? x : 0.0f;
+      }
+    }
+  };
+  auto store_plane = [&](int slot, const float (&v)[2][3]) {
+    float *base = &S.e[slot][0][0][0];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = tid + u * BX * BY;
+      if (u == 0 || t < kTile)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) base[c * kTile + t] = v[u][c];
+    }
+  };
+  auto slot_of = [&](int kk) { return (kk - k0 + 1) & 3; };
+
+  // ---- halo face of this thread (tid < kHalo), fixed over the march
+  //   [0, BX):        z-normal at (i0 + t, j0 - 1)
+  //   [BX, 2BX):      x-normal at (i0 + t - BX, j0 - 1)
+  //   [2BX, 2BX+BY):  z-normal at (i0 - 1, j0 + t - 2BX)
+  //   [2BX+BY, kHalo): y-normal at (i0 - 1, j0 + t - 2BX - BY)
+  int hcomp = 0, hr = 0, hc = 0;
+  bool hok = false;
+  uint32_t hq = 0;
+  double hs = 0.0, hti = 0.0;
+  if (tid < kHalo) {
+    int gi, gj;
+    if (tid < 2 * BX) {
+      hcomp = tid < BX ? 2 : 0;
+      const int t = tid < BX ? tid : tid - BX;
+      gi = i0 + t;
+      gj = j0 - 1;
+      hr = 0;
+      hc = t + 1;
+      hok = j0 > 0 && (hcomp == 2 ? gi < nx : gi <= nx);
+    } else {
+      hcomp = tid < 2 * BX + BY ? 2 : 1;
+      const int t = tid < 2 * BX + BY ? tid - 2 * BX : tid - 2 * BX - BY;
+      gi = i0 - 1;
+      gj = j0 + t;
+      hr = t + 1;
+      hc = 0;
+      hok = i0 > 0 && (hcomp == 2 ? gj < ny : gj <= ny);
+    }
+    if (hok) {
+      hq = uint32_t(hcomp) * cs + uint32_t(gj) * sy + uint32_t(gi);
+      // hz: (a - b) idy + (c - d) idx;  hx: (a - b) idy + (c - d) idz;  hy: (a - b) idx + (c - d) idz
+      hs = hcomp == 1 ? G.idx[gi] : G.idy[gj];
+      hti = hcomp == 2 ? G.idx[gi] : 0.0;
+    }
+  }
+
+  // ---- per-thread factors
+  const double ax[2] = {G.axl[ic], G.axh[ic]}, ay[2] = {G.ayl[jc], G.ayh[jc]};
+  const double dxi = G.idx[min(ic, nx - 1)], dhx = G.ihx[ic];
+  const double dyj = G.idy[min(jc, ny - 1)], dhy = G.ihy[jc];
+  const int pec = g.pec;
+  const bool pec_i = (i == 0 && (pec & 1)) || (i == nx && (pec & 2));
+  const bool pec_j = (j == 0 && (pec & 4)) || (j == ny && (pec & 8));
+  const bool fz_ok = active && i < nx && j < ny;  // z-normal face (i, j) exists
+
+  auto load_node = [&](int kk, YeeNode &c) {
+    const uint32_t n = uint32_t(kk) * sz + nxy;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      c.inv[d] = cf[d * cs + n];
+      c.a2[d] = cf[(3 + d) * cs + n];
+      c.K[d] = Kp ? Kp[d * cs + n] : 0.0f;
+      c.lo[d] = elo[d * cs + n];
+    }
+    c.a2xm = cf[3 * cs + (ic > 0 ? n - 1 : n)];
+    c.a2ym = cf[4 * cs + (jc > 0 ? n - sy : n)];
+    c.fl = g.flags[n] & 7;
+  };
+  auto load_hold = [&](int kk, float (&h)[3], float &hh) {
+    const uint32_t n = uint32_t(min(kk, nz)) * sz + nxy;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) h[d] = p.aux[d * cs + n];
+    if (tid < kHalo) hh = p.aux[hq + (hok ? uint32_t(min(kk, nz)) * sz : 0u)];
+  };
+
+  // ---- prologue: planes k0-1, k0, k0+1 to LDS, k0+2 to registers
+  {
+    float v0[2][3], v1[2][3], v2[2][3];
+    fetch_plane(k0 - 1, v0);
+    fetch_plane(k0, v1);
+    fetch_plane(k0 + 1, v2);
+    store_plane(slot_of(k0 - 1), v0);
+    store_plane(slot_of(k0), v1);
+    store_plane(slot_of(k0 + 1), v2);
+  }
+  float ev[2][3] = {};
+  YeeNode nd;
+  load_node(k0, nd);
+  float hold[3], hhold = 0.0f;
+  load_hold(k0, hold, hhold);
+  float a2zm = k0 > 0 ? cf[5 * cs + uint32_t(k0 - 1) * sz + nxy] : 0.0f;
+  __syncthreads();
+  // the x- and y-edges of plane k0 need the x- and y-normal faces of plane k0 - 1
+  float hy_km = 0.0f, hx_km = 0.0f;
+  if (k0 > 0) {
+    const int sm = slot_of(k0 - 1), s0 = slot_of(k0);
+    const uint32_t n = uint32_t(k0 - 1) * sz + nxy;
+    const double dzm = G.idz[k0 - 1];
+    if (active && i < nx)
+      hy_km = hface(p.aux[cs + n], S.e[sm][2][ly + 1][lx + 1], S.e[sm][2][ly + 1][lx + 2], dxi,
+                    S.e[s0][0][ly + 1][lx + 1], S.e[sm][0][ly + 1][lx + 1], dzm, cdt);
+    if (active && j < ny)
+      hx_km = hface(p.aux[n], S.e[sm][2][ly + 2][lx + 1], S.e[sm][2][ly + 1][lx + 1], dyj,
+                    S.e[sm][1][ly + 1][lx + 1], S.e[s0][1][ly + 1][lx + 1], dzm, cdt);
+  }
+
+  for (int k = k0; k < k1; ++k) {
+    const int sm = slot_of(k - 1), s0 = slot_of(k), sp = slot_of(k + 1);
+    if (k > k0) store_plane(sp, ev);
+    if (k + 2 <= k1) fetch_plane(k + 2, ev);
+    __syncthreads();
+    const int fb = k & 1;
+    const uint32_t n = uint32_t(k) * sz + nxy;
+    const double dzk = G.idz[min(k, nz - 1)], dhz = G.ihz[k];
+    const bool kin = k < nz;
+    // h^{n+1/2} on the own faces (x-, y-, z-normal at node (i, j, k))
+    const float exc = S.e[s0][0][ly + 1][lx + 1], eyc = S.e[s0][1][ly + 1][lx + 1], ezc = S.e[s0][2][ly + 1][lx + 1];
+    float hz_c = hface(hold[2], exc, S.e[s0][0][ly + 2][lx + 1], dyj, S.e[s0][1][ly + 1][lx + 2], eyc, dxi, cdt);
+    float hy_c = hface(hold[1], ezc, S.e[s0][2][ly + 1][lx + 2], dxi, S.e[sp][0][ly + 1][lx + 1], exc, dzk, cdt);
+    float hx_c = hface(hold[0], S.e[s0][2][ly + 2][lx + 1], ezc, dyj, eyc, S.e[sp][1][ly + 1][lx + 1], dzk, cdt);
+    hz_c = fz_ok ? hz_c : 0.0f;
+    hy_c = (active && i < nx && kin) ? hy_c : 0.0f;
+    hx_c = (active && j < ny && kin) ? hx_c : 0.0f;
+    S.f[fb][0][ly + 1][lx + 1] = hx_c;
+    S.f[fb][1][ly + 1][lx + 1] = hy_c;
+    S.f[fb][2][ly + 1][lx + 1] = hz_c;
+    if (fz_ok) p.oaux[2 * cs + n] = hz_c;
+    if (active && i < nx && kin) p.oaux[cs + n] = hy_c;
+    if (active && j < ny && kin) p.oaux[n] = hx_c;
+    if (tid < kHalo) {
+      // operands in LDS coordinates (r, c) of the face's node
+      const float *E0 = &S.e[s0][0][0][0], *E1 = &S.e[sp][0][0][0];
+      const int rc = hr * TXH + hc;
+      float a, b, c, d;
+      if (hcomp == 2) {  // (ex(r,c) - ex(r+1,c)) idy + (ey(r,c+1) - ey(r,c)) idx
+        a = E0[rc]; b = E0[rc + TXH]; c = E0[kTile + rc + 1]; d = E0[kTile + rc];
+      } else if (hcomp == 0) {  // (ez(r+1,c) - ez(r,c)) idy + (ey(r,c) - ey'(r,c)) idz
+        a = E0[2 * kTile + rc + TXH]; b = E0[2 * kTile + rc]; c = E0[kTile + rc]; d = E1[kTile + rc];
+      } else {  // (ez(r,c) - ez(r,c+1)) idx + (ex'(r,c) - ex(r,c)) idz
+        a = E0[2 * kTile + rc]; b = E0[2 * kTile + rc + 1]; c = E1[rc]; d = E0[rc];
+      }
+      const double t = hcomp == 2 ? hti : dzk;
+      const bool ok = hok && (hcomp == 2 || kin);
+      const float hv = hface(hhold, a, b, hs, c, d, t, cdt);
+      S.f[fb][hcomp][hr][hc] = ok ? hv : 0.0f;
+    }
+    if (k + 1 < k1) load_hold(k + 1, hold, hhold);
+    __syncthreads();
+
+    // e^{n+1} on the own x-, y-, z-edges
+    const float hz_jm = S.f[fb][2][ly][lx + 1], hx_jm = S.f[fb][0][ly][lx + 1];
+    const float hz_im = S.f[fb][2][ly + 1][lx], hy_im = S.f[fb][1][ly + 1][lx];
+    const bool pec_k = (k == 0 && (pec & 16)) || (k == nz && (pec & 32));
+    const bool pec_d[3] = {pec_j || pec_k, pec_i || pec_k, pec_i || pec_j};
+    const bool ex_d[3] = {active && i < nx, active && j < ny, active && kin};
+    const double cc[3] = {
+        (double(hz_c) - double(hz_jm)) * dhy - (double(hy_c) - double(hy_km)) * dhz,
+        (double(hx_c) - double(hx_km)) * dhz - (double(hz_c) - double(hz_im)) * dhx,
+        (double(hy_c) - double(hy_im)) * dhx - (double(hx_c) - double(hx_jm)) * dhy};
+    const float e0[3] = {exc, eyc, ezc};
+#pragma unroll
+    for (int D = 0; D < 3; ++D) {
+      const uint32_t o = D * cs + n;
+      double inv = double(nd.inv[D]), a2 = double(nd.a2[D]), jn = 0.0;
+      if (nd.fl & (1 << D)) {
+        const int q = find_port(L.ports, int64_t(D) * g.ntot + n);
+        if (q >= 0) {
+          const PortTerm pt = port_terms(L.ports, q, step);
+          const double a = 0.5 * a2 + pt.g;
+          inv = rcp64(L.ports.er[q] + a);
+          a2 = 2.0 * a;
+          jn = pt.jn;
+        }
+      }
+      const double dl = -(a2 * double(e0[D]) + cdt * cc[D] + jn - double(nd.K[D])) * inv;
+      float eh;
+      int8_t el;
+      e_split(e_join(e0[D], nd.lo[D]) + dl, eh, el);
+      if (pec_d[D]) {
+        eh = 0.0f;
+        el = 0;
+      }
+      if (ex_d[D]) {
+        p.oe[o] = eh;
+        elo[o] = el;
+      }
+    }
+    // Joule power of e^n at the node, from its six incident edges
+    if (acc_joule && active) {
+      const double az[2] = {G.azl[k], G.azh[k]};
+      const double a6[6] = {0.5 * double(nd.a2[0]), 0.5 * double(nd.a2[1]), 0.5 * double(nd.a2[2]),
+                            i > 0 ? 0.5 * double(nd.a2xm) : 0.0, j > 0 ? 0.5 * double(nd.a2ym) : 0.0,
+                            k > 0 ? 0.5 * double(a2zm) : 0.0};
+      const double v[6] = {double(exc), double(eyc), double(ezc), double(S.e[s0][0][ly + 1][lx]),
+                           double(S.e[s0][1][ly][lx + 1]), double(S.e[sm][2][ly + 1][lx + 1])};
+      const double P = node_joule(a6, ax, ay, az, v, L.jf);
+      // one thread per node: the add is not contended and its result is the plain sum
+      if (P != 0.0) unsafeAtomicAdd(L.psum + n, P);
+    }
+    hy_km = hy_c;
+    hx_km = hx_c;
+    a2zm = nd.a2[2];
+    if (k + 1 < k1) load_node(k + 1, nd);
+  }
+}
+
 // Block b of nb is dispatched to XCD b % 8; give each XCD a contiguous
 // range of logical tiles so neighbouring columns share that XCD's L2.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
@@ -510,13 +707,24 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 template <typename T, bool YEE>
+__device__ __forceinline__ void march_tile(const EmLaunch &L, const EmPtrs<T> &p, int64_t step, int tx, int ty, int kc,
+                                           int kchunk, int acc_joule) {
+  if constexpr (YEE) {
+    __shared__ YeeSmem S;
+    em_march_tile_yee(L, p, step, tx, ty, kc, kchunk, acc_joule, S);
+  } else {
+    __shared__ MarchSmem<T> S;
+    em_march_tile<T>(L, p, step, tx, ty, kc, kchunk, acc_joule, S);
+  }
+}
+
+template <typename T, bool YEE>
 __global__ __launch_bounds__(256) void em_march_kernel(EmLaunch L, EmPtrs<T> p, int ntx, int nty, int nkc, int kchunk,
                                                        int acc_joule) {
-  __shared__ MarchSmem<T> S;
   const int nb = ntx * nty * nkc;
   const int b = xcd_remap(blockIdx.x, nb);
   const int tx = b % ntx, ty = (b / ntx) % nty, kc = b / (ntx * nty);
-  em_march_tile<T, YEE>(L, p, L.step, tx, ty, kc, kchunk, acc_joule, S);
+  march_tile<T, YEE>(L, p, L.step, tx, ty, kc, kchunk, acc_joule);
 }
 
 // ---- batched: one launch walks the (variant, tile) list of all variants ----
@@ -525,7 +733,6 @@ __global__ __launch_bounds__(256) void em_march_kernel(EmLaunch L, EmPtrs<T> p, 
 template <typename T, bool YEE>
 __global__ __launch_bounds__(256) void em_march_batched(const BatchVar *vars, const int4 *items, int n_items,
                                                         const int64_t *step_ctr) {
-  __shared__ MarchSmem<T> S;
   const int b = xcd_remap(blockIdx.x, n_items);
   const int4 it = items[b];
   const BatchVar &V = vars[it.x];
@@ -546,7 +753,7 @@ __global__ __launch_bounds__(256) void em_march_batched(const BatchVar *vars, co
     p.oaux = nullptr;
   }
   const int acc = (s == 0) ? V.acc_joule0 : int(step % V.R != 0);
-  em_march_tile<T, YEE>(V.L, p, step, it.y, it.z, it.w, V.kchunk, acc, S);
+  march_tile<T, YEE>(V.L, p, step, it.y, it.z, it.w, V.kchunk, acc);
 }
 
 __global__ void step_ctr_kernel(int64_t *ctr, int64_t v, int set) {
