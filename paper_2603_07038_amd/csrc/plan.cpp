@@ -474,8 +474,10 @@ etm_status derive(etm_plan *p, const etm_source *src) {
         if (p->r_K[c].off - p->r_K[c - 1].off != size_t(p->comp_stride) * esz) return fail(ETM_E_INVAL, "layout");
     for (int c = 1; c < 6; ++c)
       if (p->r_coef[c].off - p->r_coef[c - 1].off != size_t(p->comp_stride) * esz) return fail(ETM_E_INVAL, "layout");
-    if (p->ntot + 2 * p->comp_stride >= (int64_t(1) << 32))
-      return fail(ETM_E_INVAL, "mesh too large for 32-bit node offsets (padded nodes must stay below 1.4e9)");
+    // the march kernels index component c of a field as c * stride + node in
+    // 32 bits (coefficients up to c = 5)
+    if (p->ntot + 5 * p->comp_stride >= (int64_t(1) << 32))
+      return fail(ETM_E_INVAL, "mesh too large for 32-bit node offsets (padded nodes must stay below 7.1e8)");
   }
   return ETM_OK;
 }
