@@ -104,10 +104,10 @@ etm_status rebuild(etm_batch *b) {
     etm_plan *p = b->slots[b->order[v]];
     const DevGrid g = p->dev_grid();
     auto it = b->kchunk_by_class.find(size_class(p));
-    const int kc = it != b->kchunk_by_class.end() ? it->second : em_kchunk(g);
+    const int kc = it != b->kchunk_by_class.end() ? it->second : em_kchunk(g, b->precision);
     p->kchunk = kc;
     int ntx, nty, nkc;
-    em_tiles(g, kc, &ntx, &nty, &nkc);
+    em_tiles(g, b->precision, kc, &ntx, &nty, &nkc);
     for (int c = 0; c < nkc; ++c)
       for (int y = 0; y < nty; ++y)
         for (int x = 0; x < ntx; ++x) items.push_back(make_int4(int(v), x, y, c));

@@ -11,13 +11,13 @@
 // (curl mu0^-1 curl = C / mu0) and jd = dt (J^{n+1/2} - J^{n-1/2}) / eps0.
 // The mixed path marches the same scheme as leapfrog on (e^n, h^{n-1/2}),
 // both stored in FP32 and combined in FP64, with an 8-bit residual that
-// extends the stored e below its FP32 rounding (em_march_tile_yee).  Edge
+// extends the stored e below its FP32 rounding (em_march_row_yee).  Edge
 // coefficients are always formed in FP64 and rounded once.
 //
-// March kernels.  A block owns a 64 x 4 column of nodes and marches up a
-// chunk of z planes, staging e planes with a one-node halo in LDS, so each e
-// value is fetched from memory once per step.  A node updates the x-, y- and
-// z-edges that start at it.  The Joule source is gathered one step late: the
+// March kernels.  A block owns a column of 4 rows of nodes and marches up a
+// chunk of z planes (FP64: 64 x 4 nodes staged in LDS with a one-node halo;
+// mixed: one barrier-free wave per row of 62 nodes).  A node updates the x-,
+// y- and z-edges that start at it.  The Joule source is gathered one step late: the
 // node sums sigma e^2 L A over its six incident edges of the *input* field
 // e^n, which the stencil already holds, so no edge update is recomputed.
 // The power of the last step of a thermal block is added by the thermal
@@ -423,21 +423,6 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
 // never feed the gradient (static-charge) modes the curl-curl leaves
 // undamped in dielectrics; the increment form e^{n+1} - e^n stored in FP32
 // lets them accumulate.
-//
-// Per z plane a block first forms the h faces of its 64 x 4 nodes (each
-// thread its own three, and 136 threads the faces of the low-side halo
-// row and column that the edge update needs), puts them in LDS, then
-// updates the three own edges of every node.  Every face is computed once
-// per block with one expression, so a face at a tile or chunk border is
-// bitwise the value its owner stores.  A four-plane e ring and two face
-// buffers need two barriers per plane; the next e plane and the next plane's
-// per-node inputs are fetched into registers while the current plane is
-// computed.
-struct YeeSmem {
-  float e[4][3][TYH][TXH];        // e^n (FP32 part), planes k-1 .. k+2 in a ring
-  float f[2][3][BY + 1][BX + 1];  // h^{n+1/2} of plane k: [x-, y-, z-normal][j - j0 + 1][i - i0 + 1]
-};
-constexpr int kHalo = 2 * BX + 2 * BY;  // halo faces: z- and x-normal of row j0-1, z- and y-normal of column i0-1
 
 // Per-node inputs of one plane for the edge update.
 struct YeeNode {
@@ -447,109 +432,77 @@ struct YeeNode {
   uint8_t fl;
 };
 
-__device__ __forceinline__ void em_march_tile_yee(const EmLaunch &L, const EmPtrs<float> &p, int64_t step, int tx,
-                                                  int ty, int kc, int kchunk, int acc_joule, YeeSmem &S) {
+// One wave per x-row, no barriers.  A wave owns WX = 62 consecutive nodes
+// of one row (j, k) and marches up its z-chunk on its own: lane L holds node i = WX * ts - 1 + L, so lanes 0 and
+// 63 overlap the neighbouring segments and every x-neighbour a face or the
+// Joule gather needs is one lane away (whole-wave DPP shifts).  The rows
+// j - 1 and j + 1 are read directly (their own waves read the same lines,
+// so they are L2 hits), the faces of row j - 1 that the edge update needs are
+// recomputed in-wave with the same expression their owner uses, and the y
+// factors of the row are wave-uniform.  No LDS and no barriers: each wave's
+// loads for the next plane are in flight while it computes the current one,
+// and its neighbours on the SIMD fill the gaps.
+constexpr int WX = 62;
+
+__device__ __forceinline__ float lane_next(float v) {  // value of lane + 1 (0 past the last lane)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_prev(float v) {  // value of lane - 1 (0 before the first lane)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+
+struct RowE {  // e of one row and plane (x, y, z components)
+  float x, y, z;
+};
+
+__device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs<float> &p, int64_t step, int ts,
+                                                 int tr, int kc, int kchunk, int acc_joule) {
   const DevGrid &g = L.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const uint32_t sy = uint32_t(g.sy), sz = uint32_t(g.sz), cs = g.cs;
+  const int lane = threadIdx.x;
+  const int j = tr * BY + __builtin_amdgcn_readfirstlane(int(threadIdx.y));  // wave-uniform row
+  if (j > ny) return;
   const Geo G(g.geo, nx, ny, nz);
   const float *cf = static_cast<const float *>(L.coef);
   const float *Kp = L.K;
   int8_t *elo = L.elo;
   const double cdt = L.cdt;
-  const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * BX + lx;
-  const int i0 = tx * BX, j0 = ty * BY;
-  const int i = i0 + lx, j = j0 + ly;
+  const int i = WX * ts - 1 + lane;
+  const bool inb = i >= 0 && i <= nx;                       // node exists
+  const bool own = lane >= 1 && lane <= WX && i <= nx;      // node updated by this lane
+  const int ic = min(max(i, 0), nx);
   const int k0 = kc * kchunk, k1 = min(k0 + kchunk, nz + 1);
-  const bool active = i <= nx && j <= ny;
-  const int ic = min(i, nx), jc = min(j, ny);
-  const uint32_t nxy = uint32_t(jc) * sy + uint32_t(ic);  // clamped: every load below is in bounds
+  const bool jm_ok = j > 0, jp_ok = j < ny;                 // rows j - 1, j + 1 exist
+  const uint32_t rj = uint32_t(j) * sy + uint32_t(ic);
+  const uint32_t rm = jm_ok ? rj - sy : rj, rp = jp_ok ? rj + sy : rj;
 
-  // ---- e plane staging: entries tid and tid + 256 of the TYH x TXH tile
-  constexpr int kTile = TYH * TXH;
-  static_assert(kTile <= 2 * BX * BY, "two staging entries per thread");
-  uint32_t qxy[2];
-  bool okxy[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int t = tid + u * BX * BY;
-    const int r = t / TXH, c = t - r * TXH;
-    const int gi = i0 - 1 + c, gj = j0 - 1 + r;
-    okxy[u] = t < kTile && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny;
-    qxy[u] = okxy[u] ? uint32_t(gj) * sy + uint32_t(gi) : 0u;
-  }
-  auto fetch_plane = [&](int kk, float (&v)[2][3]) {
-    const bool okz = kk >= 0 && kk <= nz;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const bool ok = okz && okxy[u];
-      const uint32_t q = ok ? uint32_t(kk) * sz + qxy[u] : 0u;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float x = p.e[c * cs + q];
-        v[u][c] = ok ? x : 0.0f;
-      }
-    }
+  auto ld = [&](const float *base, int kk, uint32_t r, bool ok) -> float {
+    const bool v = ok && inb && kk >= 0 && kk <= nz;
+    const float x = base[v ? uint32_t(kk) * sz + r : 0u];
+    return v ? x : 0.0f;
   };
-  auto store_plane = [&](int slot, const float (&v)[2][3]) {
-    float *base = &S.e[slot][0][0][0];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = tid + u * BX * BY;
-      if (u == 0 || t < kTile)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) base[c * kTile + t] = v[u][c];
-    }
+  auto row3 = [&](int kk, uint32_t r, bool ok) -> RowE {
+    return RowE{ld(p.e, kk, r, ok), ld(p.e + cs, kk, r, ok), ld(p.e + 2 * cs, kk, r, ok)};
   };
-  auto slot_of = [&](int kk) { return (kk - k0 + 1) & 3; };
 
-  // ---- halo face of this thread (tid < kHalo), fixed over the march
-  //   [0, BX):        z-normal at (i0 + t, j0 - 1)
-  //   [BX, 2BX):      x-normal at (i0 + t - BX, j0 - 1)
-  //   [2BX, 2BX+BY):  z-normal at (i0 - 1, j0 + t - 2BX)
-  //   [2BX+BY, kHalo): y-normal at (i0 - 1, j0 + t - 2BX - BY)
-  int hcomp = 0, hr = 0, hc = 0;
-  bool hok = false;
-  uint32_t hq = 0;
-  double hs = 0.0, hti = 0.0;
-  if (tid < kHalo) {
-    int gi, gj;
-    if (tid < 2 * BX) {
-      hcomp = tid < BX ? 2 : 0;
-      const int t = tid < BX ? tid : tid - BX;
-      gi = i0 + t;
-      gj = j0 - 1;
-      hr = 0;
-      hc = t + 1;
-      hok = j0 > 0 && (hcomp == 2 ? gi < nx : gi <= nx);
-    } else {
-      hcomp = tid < 2 * BX + BY ? 2 : 1;
-      const int t = tid < 2 * BX + BY ? tid - 2 * BX : tid - 2 * BX - BY;
-      gi = i0 - 1;
-      gj = j0 + t;
-      hr = t + 1;
-      hc = 0;
-      hok = i0 > 0 && (hcomp == 2 ? gj < ny : gj <= ny);
-    }
-    if (hok) {
-      hq = uint32_t(hcomp) * cs + uint32_t(gj) * sy + uint32_t(gi);
-      // hz: (a - b) idy + (c - d) idx;  hx: (a - b) idy + (c - d) idz;  hy: (a - b) idx + (c - d) idz
-      hs = hcomp == 1 ? G.idx[gi] : G.idy[gj];
-      hti = hcomp == 2 ? G.idx[gi] : 0.0;
-    }
-  }
-
-  // ---- per-thread factors
-  const double ax[2] = {G.axl[ic], G.axh[ic]}, ay[2] = {G.ayl[jc], G.ayh[jc]};
+  // per-lane x factors, per-wave y factors
   const double dxi = G.idx[min(ic, nx - 1)], dhx = G.ihx[ic];
-  const double dyj = G.idy[min(jc, ny - 1)], dhy = G.ihy[jc];
+  const double ax[2] = {G.axl[ic], G.axh[ic]};
+  const double dyj = G.idy[min(j, ny - 1)], dym = G.idy[max(j - 1, 0)], dhy = G.ihy[j];
+  const double ay[2] = {G.ayl[j], G.ayh[j]};
   const int pec = g.pec;
   const bool pec_i = (i == 0 && (pec & 1)) || (i == nx && (pec & 2));
   const bool pec_j = (j == 0 && (pec & 4)) || (j == ny && (pec & 8));
-  const bool fz_ok = active && i < nx && j < ny;  // z-normal face (i, j) exists
+  // faces that exist (independent of the plane, apart from k < nz)
+  const bool fz = inb && i < nx && j < ny;         // z-normal (i, j)
+  const bool fzm = inb && i < nx && jm_ok;         // z-normal (i, j - 1)
+  const bool fy = inb && i < nx;                   // y-normal (i, j, k), k < nz
+  const bool fx = inb && j < ny;                   // x-normal (i, j, k), k < nz
+  const bool fxm = inb && jm_ok;                   // x-normal (i, j - 1, k), k < nz
 
   auto load_node = [&](int kk, YeeNode &c) {
-    const uint32_t n = uint32_t(kk) * sz + nxy;
+    const uint32_t n = uint32_t(kk) * sz + rj;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       c.inv[d] = cf[d * cs + n];
@@ -557,105 +510,90 @@ __device__ __forceinline__ void em_march_tile_yee(const EmLaunch &L, const EmPtr
       c.K[d] = Kp ? Kp[d * cs + n] : 0.0f;
       c.lo[d] = elo[d * cs + n];
     }
-    c.a2xm = cf[3 * cs + (ic > 0 ? n - 1 : n)];
-    c.a2ym = cf[4 * cs + (jc > 0 ? n - sy : n)];
+    c.a2xm = 0.0f;  // from the previous lane
+    c.a2ym = cf[4 * cs + uint32_t(kk) * sz + rm];
     c.fl = g.flags[n] & 7;
   };
-  auto load_hold = [&](int kk, float (&h)[3], float &hh) {
-    const uint32_t n = uint32_t(min(kk, nz)) * sz + nxy;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) h[d] = p.aux[d * cs + n];
-    if (tid < kHalo) hh = p.aux[hq + (hok ? uint32_t(min(kk, nz)) * sz : 0u)];
+  struct Hold {
+    float x, y, z, xm, zm;  // old faces at (i, j, k) and at (i, j - 1, k)
+  };
+  auto load_hold = [&](int kk, Hold &h) {
+    const uint32_t kz = uint32_t(min(kk, nz)) * sz, n = kz + rj, m = kz + rm;
+    h.x = p.aux[n];
+    h.y = p.aux[cs + n];
+    h.z = p.aux[2 * cs + n];
+    h.xm = p.aux[m];
+    h.zm = p.aux[2 * cs + m];
   };
 
-  // ---- prologue: planes k0-1, k0, k0+1 to LDS, k0+2 to registers
-  {
-    float v0[2][3], v1[2][3], v2[2][3];
-    fetch_plane(k0 - 1, v0);
-    fetch_plane(k0, v1);
-    fetch_plane(k0 + 1, v2);
-    store_plane(slot_of(k0 - 1), v0);
-    store_plane(slot_of(k0), v1);
-    store_plane(slot_of(k0 + 1), v2);
-  }
-  float ev[2][3] = {};
+  // ---- prologue
+  RowE c0 = row3(k0, rj, true), m0 = row3(k0, rm, jm_ok);
+  RowE c1 = row3(k0 + 1, rj, true), m1 = row3(k0 + 1, rm, jm_ok);
+  float p0x = ld(p.e, k0, rp, jp_ok), p0z = ld(p.e + 2 * cs, k0, rp, jp_ok);
+  float p1x = ld(p.e, k0 + 1, rp, jp_ok), p1z = ld(p.e + 2 * cs, k0 + 1, rp, jp_ok);
   YeeNode nd;
   load_node(k0, nd);
-  float hold[3], hhold = 0.0f;
-  load_hold(k0, hold, hhold);
-  float a2zm = k0 > 0 ? cf[5 * cs + uint32_t(k0 - 1) * sz + nxy] : 0.0f;
-  __syncthreads();
-  // the x- and y-edges of plane k0 need the x- and y-normal faces of plane k0 - 1
-  float hy_km = 0.0f, hx_km = 0.0f;
+  Hold ho;
+  load_hold(k0, ho);
+  float ezm = 0.0f, hy_km = 0.0f, hx_km = 0.0f, a2zm = 0.0f;
   if (k0 > 0) {
-    const int sm = slot_of(k0 - 1), s0 = slot_of(k0);
-    const uint32_t n = uint32_t(k0 - 1) * sz + nxy;
+    // the x- and y-edges of plane k0 need the x- and y-normal faces of plane k0 - 1
+    const RowE cm = row3(k0 - 1, rj, true);
+    const float pmz = ld(p.e + 2 * cs, k0 - 1, rp, jp_ok);
+    const uint32_t n = uint32_t(k0 - 1) * sz + rj;
     const double dzm = G.idz[k0 - 1];
-    if (active && i < nx)
-      hy_km = hface(p.aux[cs + n], S.e[sm][2][ly + 1][lx + 1], S.e[sm][2][ly + 1][lx + 2], dxi,
-                    S.e[s0][0][ly + 1][lx + 1], S.e[sm][0][ly + 1][lx + 1], dzm, cdt);
-    if (active && j < ny)
-      hx_km = hface(p.aux[n], S.e[sm][2][ly + 2][lx + 1], S.e[sm][2][ly + 1][lx + 1], dyj,
-                    S.e[sm][1][ly + 1][lx + 1], S.e[s0][1][ly + 1][lx + 1], dzm, cdt);
+    const float hy = hface(p.aux[cs + n], cm.z, lane_next(cm.z), dxi, c0.x, cm.x, dzm, cdt);
+    const float hx = hface(p.aux[n], pmz, cm.z, dyj, cm.y, c0.y, dzm, cdt);
+    hy_km = fy ? hy : 0.0f;
+    hx_km = fx ? hx : 0.0f;
+    ezm = cm.z;
+    a2zm = cf[5 * cs + n];
   }
 
+#pragma unroll 2
   for (int k = k0; k < k1; ++k) {
-    const int sm = slot_of(k - 1), s0 = slot_of(k), sp = slot_of(k + 1);
-    if (k > k0) store_plane(sp, ev);
-    if (k + 2 <= k1) fetch_plane(k + 2, ev);
-    __syncthreads();
-    const int fb = k & 1;
-    const uint32_t n = uint32_t(k) * sz + nxy;
-    const double dzk = G.idz[min(k, nz - 1)], dhz = G.ihz[k];
-    const bool kin = k < nz;
-    // h^{n+1/2} on the own faces (x-, y-, z-normal at node (i, j, k))
-    const float exc = S.e[s0][0][ly + 1][lx + 1], eyc = S.e[s0][1][ly + 1][lx + 1], ezc = S.e[s0][2][ly + 1][lx + 1];
-    float hz_c = hface(hold[2], exc, S.e[s0][0][ly + 2][lx + 1], dyj, S.e[s0][1][ly + 1][lx + 2], eyc, dxi, cdt);
-    float hy_c = hface(hold[1], ezc, S.e[s0][2][ly + 1][lx + 2], dxi, S.e[sp][0][ly + 1][lx + 1], exc, dzk, cdt);
-    float hx_c = hface(hold[0], S.e[s0][2][ly + 2][lx + 1], ezc, dyj, eyc, S.e[sp][1][ly + 1][lx + 1], dzk, cdt);
-    hz_c = fz_ok ? hz_c : 0.0f;
-    hy_c = (active && i < nx && kin) ? hy_c : 0.0f;
-    hx_c = (active && j < ny && kin) ? hx_c : 0.0f;
-    S.f[fb][0][ly + 1][lx + 1] = hx_c;
-    S.f[fb][1][ly + 1][lx + 1] = hy_c;
-    S.f[fb][2][ly + 1][lx + 1] = hz_c;
-    if (fz_ok) p.oaux[2 * cs + n] = hz_c;
-    if (active && i < nx && kin) p.oaux[cs + n] = hy_c;
-    if (active && j < ny && kin) p.oaux[n] = hx_c;
-    if (tid < kHalo) {
-      // operands in LDS coordinates (r, c) of the face's node
-      const float *E0 = &S.e[s0][0][0][0], *E1 = &S.e[sp][0][0][0];
-      const int rc = hr * TXH + hc;
-      float a, b, c, d;
-      if (hcomp == 2) {  // (ex(r,c) - ex(r+1,c)) idy + (ey(r,c+1) - ey(r,c)) idx
-        a = E0[rc]; b = E0[rc + TXH]; c = E0[kTile + rc + 1]; d = E0[kTile + rc];
-      } else if (hcomp == 0) {  // (ez(r+1,c) - ez(r,c)) idy + (ey(r,c) - ey'(r,c)) idz
-        a = E0[2 * kTile + rc + TXH]; b = E0[2 * kTile + rc]; c = E0[kTile + rc]; d = E1[kTile + rc];
-      } else {  // (ez(r,c) - ez(r,c+1)) idx + (ex'(r,c) - ex(r,c)) idz
-        a = E0[2 * kTile + rc]; b = E0[2 * kTile + rc + 1]; c = E1[rc]; d = E0[rc];
-      }
-      const double t = hcomp == 2 ? hti : dzk;
-      const bool ok = hok && (hcomp == 2 || kin);
-      const float hv = hface(hhold, a, b, hs, c, d, t, cdt);
-      S.f[fb][hcomp][hr][hc] = ok ? hv : 0.0f;
+    // next plane's e in flight while this plane is computed
+    RowE c2{0.0f, 0.0f, 0.0f}, m2{0.0f, 0.0f, 0.0f};
+    float p2x = 0.0f, p2z = 0.0f;
+    if (k + 2 <= k1) {
+      c2 = row3(k + 2, rj, true);
+      m2 = row3(k + 2, rm, jm_ok);
+      p2x = ld(p.e, k + 2, rp, jp_ok);
+      p2z = ld(p.e + 2 * cs, k + 2, rp, jp_ok);
     }
-    if (k + 1 < k1) load_hold(k + 1, hold, hhold);
-    __syncthreads();
+    const uint32_t n = uint32_t(k) * sz + rj;
+    const double dzk = G.idz[min(k, nz - 1)], dhz = G.ihz[k];
+    const double az[2] = {G.azl[k], G.azh[k]};
+    const bool kin = k < nz;
+    // h^{n+1/2}: own faces and the z- and x-normal faces of row j - 1
+    const float ey_n = lane_next(c0.y), ez_n = lane_next(c0.z), eym_n = lane_next(m0.y);
+    float hz_c = hface(ho.z, c0.x, p0x, dyj, ey_n, c0.y, dxi, cdt);
+    float hy_c = hface(ho.y, c0.z, ez_n, dxi, c1.x, c0.x, dzk, cdt);
+    float hx_c = hface(ho.x, p0z, c0.z, dyj, c0.y, c1.y, dzk, cdt);
+    float hz_jm = hface(ho.zm, m0.x, c0.x, dym, eym_n, m0.y, dxi, cdt);
+    float hx_jm = hface(ho.xm, c0.z, m0.z, dym, m0.y, m1.y, dzk, cdt);
+    hz_c = fz ? hz_c : 0.0f;
+    hy_c = (fy && kin) ? hy_c : 0.0f;
+    hx_c = (fx && kin) ? hx_c : 0.0f;
+    hz_jm = fzm ? hz_jm : 0.0f;
+    hx_jm = (fxm && kin) ? hx_jm : 0.0f;
+    const float hz_im = lane_prev(hz_c), hy_im = lane_prev(hy_c);
+    if (own && fz) p.oaux[2 * cs + n] = hz_c;
+    if (own && fy && kin) p.oaux[cs + n] = hy_c;
+    if (own && fx && kin) p.oaux[n] = hx_c;
+    if (k + 1 < k1) load_hold(k + 1, ho);
 
     // e^{n+1} on the own x-, y-, z-edges
-    const float hz_jm = S.f[fb][2][ly][lx + 1], hx_jm = S.f[fb][0][ly][lx + 1];
-    const float hz_im = S.f[fb][2][ly + 1][lx], hy_im = S.f[fb][1][ly + 1][lx];
     const bool pec_k = (k == 0 && (pec & 16)) || (k == nz && (pec & 32));
     const bool pec_d[3] = {pec_j || pec_k, pec_i || pec_k, pec_i || pec_j};
-    const bool ex_d[3] = {active && i < nx, active && j < ny, active && kin};
+    const bool ex_d[3] = {own && i < nx, own && j < ny, own && kin};
     const double cc[3] = {
         (double(hz_c) - double(hz_jm)) * dhy - (double(hy_c) - double(hy_km)) * dhz,
         (double(hx_c) - double(hx_km)) * dhz - (double(hz_c) - double(hz_im)) * dhx,
         (double(hy_c) - double(hy_im)) * dhx - (double(hx_c) - double(hx_jm)) * dhy};
-    const float e0[3] = {exc, eyc, ezc};
+    const float e0[3] = {c0.x, c0.y, c0.z};
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
-      const uint32_t o = D * cs + n;
       double inv = double(nd.inv[D]), a2 = double(nd.a2[D]), jn = 0.0;
       if (nd.fl & (1 << D)) {
         const int q = find_port(L.ports, int64_t(D) * g.ntot + n);
@@ -676,26 +614,29 @@ __device__ __forceinline__ void em_march_tile_yee(const EmLaunch &L, const EmPtr
         el = 0;
       }
       if (ex_d[D]) {
-        p.oe[o] = eh;
-        elo[o] = el;
+        p.oe[D * cs + n] = eh;
+        elo[D * cs + n] = el;
       }
     }
     // Joule power of e^n at the node, from its six incident edges
-    if (acc_joule && active) {
-      const double az[2] = {G.azl[k], G.azh[k]};
+    const float a2xm = lane_prev(nd.a2[0]), exm = lane_prev(c0.x);
+    if (acc_joule && own) {
       const double a6[6] = {0.5 * double(nd.a2[0]), 0.5 * double(nd.a2[1]), 0.5 * double(nd.a2[2]),
-                            i > 0 ? 0.5 * double(nd.a2xm) : 0.0, j > 0 ? 0.5 * double(nd.a2ym) : 0.0,
+                            i > 0 ? 0.5 * double(a2xm) : 0.0, jm_ok ? 0.5 * double(nd.a2ym) : 0.0,
                             k > 0 ? 0.5 * double(a2zm) : 0.0};
-      const double v[6] = {double(exc), double(eyc), double(ezc), double(S.e[s0][0][ly + 1][lx]),
-                           double(S.e[s0][1][ly][lx + 1]), double(S.e[sm][2][ly + 1][lx + 1])};
+      const double v[6] = {double(c0.x), double(c0.y), double(c0.z), double(exm), double(m0.y), double(ezm)};
       const double P = node_joule(a6, ax, ay, az, v, L.jf);
       // one thread per node: the add is not contended and its result is the plain sum
       if (P != 0.0) unsafeAtomicAdd(L.psum + n, P);
     }
+    ezm = c0.z;
     hy_km = hy_c;
     hx_km = hx_c;
     a2zm = nd.a2[2];
     if (k + 1 < k1) load_node(k + 1, nd);
+    c0 = c1; c1 = c2;
+    m0 = m1; m1 = m2;
+    p0x = p1x; p0z = p1z; p1x = p2x; p1z = p2z;
   }
 }
 
@@ -710,8 +651,7 @@ template <typename T, bool YEE>
 __device__ __forceinline__ void march_tile(const EmLaunch &L, const EmPtrs<T> &p, int64_t step, int tx, int ty, int kc,
                                            int kchunk, int acc_joule) {
   if constexpr (YEE) {
-    __shared__ YeeSmem S;
-    em_march_tile_yee(L, p, step, tx, ty, kc, kchunk, acc_joule, S);
+    em_march_row_yee(L, p, step, tx, ty, kc, kchunk, acc_joule);
   } else {
     __shared__ MarchSmem<T> S;
     em_march_tile<T>(L, p, step, tx, ty, kc, kchunk, acc_joule, S);
@@ -1052,17 +992,18 @@ __global__ void fill_kernel(uint32_t *dst, int64_t n_words) {
 
 }  // namespace
 
-void em_tiles(const DevGrid &g, int kchunk, int *ntx, int *nty, int *nkc) {
-  *ntx = (g.nx + 1 + BX - 1) / BX;
+void em_tiles(const DevGrid &g, int precision, int kchunk, int *ntx, int *nty, int *nkc) {
+  const int wx = precision == ETM_PREC_MIXED ? WX : BX;  // nodes a block owns along x
+  *ntx = (g.nx + 1 + wx - 1) / wx;
   *nty = (g.ny + 1 + BY - 1) / BY;
   *nkc = (g.nz + 1 + kchunk - 1) / kchunk;
 }
 
-int em_kchunk(const DevGrid &g) {
+int em_kchunk(const DevGrid &g, int precision) {
   // Enough blocks to fill 256 CUs several times over, with chunks long
   // enough that the two extra planes staged per chunk stay cheap.
   int ntx, nty, nkc;
-  em_tiles(g, 1, &ntx, &nty, &nkc);
+  em_tiles(g, precision, 1, &ntx, &nty, &nkc);
   const int64_t cols = int64_t(ntx) * nty;
   int kc = 16;
   while (kc > 4 && cols * ((g.nz + 1 + kc - 1) / kc) < 2048) kc /= 2;
@@ -1071,8 +1012,8 @@ int em_kchunk(const DevGrid &g) {
 
 hipError_t launch_em_step(const EmLaunch &L, hipStream_t s) {
   int ntx, nty, nkc;
-  const int kc = L.kchunk > 0 ? L.kchunk : em_kchunk(L.g);
-  em_tiles(L.g, kc, &ntx, &nty, &nkc);
+  const int kc = L.kchunk > 0 ? L.kchunk : em_kchunk(L.g, L.precision);
+  em_tiles(L.g, L.precision, kc, &ntx, &nty, &nkc);
   const int nb = ntx * nty * nkc;
   const dim3 block(BX, BY, 1);
   if (L.precision == ETM_PREC_FP64) {

@@ -123,8 +123,10 @@ struct CoefK {
 };
 hipError_t launch_coef(const DevGrid &g, const DevPorts &P, int precision, const void *theta, void *coef, CoefK ck,
                        hipStream_t s);
-void em_tiles(const DevGrid &g, int kchunk, int *ntx, int *nty, int *nkc);
-int em_kchunk(const DevGrid &g);
+// Tile counts of the march kernels (x segments, y rows of blocks, z chunks)
+// and the default z-chunk, per precision.
+void em_tiles(const DevGrid &g, int precision, int kchunk, int *ntx, int *nty, int *nkc);
+int em_kchunk(const DevGrid &g, int precision);
 
 // One variant of a batch: its grid, constants and state buffers; the step
 // offset within the advance call is read from a device counter.
