@@ -100,15 +100,47 @@ typedef struct {
     double weight, g;
 } etm_port;
 
-/* Sampled excitations: J_half[w*n_samples + s] = J_w((s - 1/2) dt), so EM
- * step n (making e^{n+1}) uses samples n+1 and n; samples beyond the array
- * are taken as zero.  Column 0 (t = -dt/2) is zero for a causal source. */
+/* Closed-form excitation waveforms, evaluated on the device at every EM step
+ * (the transient excitation scheme of Sec. 3.3: a Ricker trigger, a sine
+ * "logic noise" and a Gaussian-pulse-train "data burst" on a carrier, each
+ * with its own per-port amplitude, width and phase).  A wave is zero outside
+ * [t_on, t_off); inside, with u = (t - t0) / width:
+ *   ETM_WAVE_RICKER       amp * (1 - 2 u^2) * exp(-u^2)
+ *   ETM_WAVE_SINE         amp * sin(2 pi freq (t - t0))
+ *   ETM_WAVE_GAUSS_TRAIN  amp * cos(2 pi freq (t - t0)) * sum_p exp(-((t - pulse_t[p]) / width)^2),
+ *                         p < n_pulses
+ * Times in seconds, freq in Hz; amp in the unit of the port weight's
+ * counterpart (A/m^2 for a current port of weight 1, V for a voltage port).
+ * Validation at etm_plan_create: kind known, width > 0 where used,
+ * 1 <= n_pulses <= ETM_WAVE_MAX_PULSES for trains, t_on <= t_off (an empty
+ * window is a wave that is always zero), all values finite; else
+ * ETM_E_INVAL. */
+enum { ETM_WAVE_RICKER = 1, ETM_WAVE_SINE = 2, ETM_WAVE_GAUSS_TRAIN = 3 };
+#define ETM_WAVE_MAX_PULSES 8
+typedef struct {
+    int32_t kind;
+    int32_t n_pulses;
+    double amp, t0, width, freq, t_on, t_off;
+    double pulse_t[ETM_WAVE_MAX_PULSES];
+} etm_wave;
+
+/* Excitations.  Sampled waves: J_half[w*n_samples + s] = J_w((s - 1/2) dt),
+ * so EM step n (making e^{n+1}) uses samples n+1 and n; samples beyond the
+ * array are taken as zero.  Column 0 (t = -dt/2) is zero for a causal
+ * source.  Closed-form waves (analytic, may be null when n_analytic = 0)
+ * follow the sampled ones: a port's wave index w < n_waves names sampled
+ * wave w, n_waves <= w < n_waves + n_analytic names analytic[w - n_waves],
+ * evaluated at t = (n + 1/2) dt and (n - 1/2) dt for step n.  All arrays
+ * are copied at etm_plan_create. */
 typedef struct {
     int64_t n_ports;
     const etm_port *ports;
     int32_t n_waves;
     int64_t n_samples;
     const double *J_half;
+    int32_t n_analytic;
+    int32_t reserved;
+    const etm_wave *analytic;
 } etm_source;
 
 /* Run options.  Fill with etm_opts_default() first. */

@@ -47,9 +47,20 @@ class etm_port(C.Structure):
                 ("reserved", C.c_int32), ("weight", C.c_double), ("g", C.c_double)]
 
 
+ETM_WAVE_RICKER, ETM_WAVE_SINE, ETM_WAVE_GAUSS_TRAIN = 1, 2, 3
+ETM_WAVE_MAX_PULSES = 8
+
+
+class etm_wave(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_pulses", C.c_int32), ("amp", C.c_double), ("t0", C.c_double),
+                ("width", C.c_double), ("freq", C.c_double), ("t_on", C.c_double), ("t_off", C.c_double),
+                ("pulse_t", C.c_double * ETM_WAVE_MAX_PULSES)]
+
+
 class etm_source(C.Structure):
     _fields_ = [("n_ports", C.c_int64), ("ports", C.POINTER(etm_port)), ("n_waves", C.c_int32),
-                ("n_samples", C.c_int64), ("J_half", C.POINTER(C.c_double))]
+                ("n_samples", C.c_int64), ("J_half", C.POINTER(C.c_double)), ("n_analytic", C.c_int32),
+                ("reserved", C.c_int32), ("analytic", C.POINTER(etm_wave))]
 
 
 class etm_opts(C.Structure):
@@ -144,7 +155,7 @@ def _dp(a):
 class _Inputs:
     """Keeps the ctypes views of a problem's arrays alive for one call."""
 
-    def __init__(self, prob, J_half):
+    def __init__(self, prob, J_half, device_waves=False):
         self.dx = np.ascontiguousarray(prob.dx, dtype=np.float64)
         self.dy = np.ascontiguousarray(prob.dy, dtype=np.float64)
         self.dz = np.ascontiguousarray(prob.dz, dtype=np.float64)
@@ -161,8 +172,19 @@ class _Inputs:
             self.ports[q] = etm_port(int(prob.port_dir[q]), int(prob.port_i[q]), int(prob.port_j[q]),
                                      int(prob.port_k[q]), int(prob.port_wave[q]), 0, float(prob.port_weight[q]),
                                      float(prob.port_g[q]))
-        self.J = np.ascontiguousarray(J_half, dtype=np.float64) if J_half is not None else np.zeros((1, 1))
-        self.src = etm_source(n, self.ports, int(self.J.shape[0]), int(self.J.shape[1]), _dp(self.J))
+        if device_waves:
+            # every wave as a closed-form record evaluated on the device; no table
+            self.waves = (etm_wave * max(len(prob.waves), 1))()
+            for w, wave in enumerate(prob.waves):
+                d = wave.device_params()
+                pt = (C.c_double * ETM_WAVE_MAX_PULSES)(*[float(x) for x in d["pulse_t"]][:ETM_WAVE_MAX_PULSES])
+                self.waves[w] = etm_wave(d["kind"], d["n_pulses"], float(d["amp"]), float(d["t0"]), float(d["width"]),
+                                         float(d["freq"]), float(d["t_on"]), float(d["t_off"]), pt)
+            self.J = np.zeros((1, 1))
+            self.src = etm_source(n, self.ports, 0, 0, _dp(self.J), len(prob.waves), 0, self.waves)
+        else:
+            self.J = np.ascontiguousarray(J_half, dtype=np.float64) if J_half is not None else np.zeros((1, 1))
+            self.src = etm_source(n, self.ports, int(self.J.shape[0]), int(self.J.shape[1]), _dp(self.J), 0, 0, None)
 
 
 def make_opts(prob, *, dt=0.0, precision=ETM_PREC_FP64, n_steps=None, mech_mask=None, force_dt=False,
@@ -207,11 +229,14 @@ def cfl_dt(prob, cfl=None):
 class Plan:
     """One design on the GPU: etm_plan_create + a torch workspace + bind."""
 
-    def __init__(self, prob, J_half, *, device="cuda", stream=None, bind=True, **opt_kw):
+    def __init__(self, prob, J_half, *, device="cuda", stream=None, bind=True, device_waves=False, **opt_kw):
+        """J_half: sampled waves [n_waves][n_steps + 1] (see Problem.sample_J_half),
+        or None with device_waves=True, where every wave of the problem is
+        passed as a closed-form record and evaluated on the device."""
         import torch
         L = load()
         self.prob = prob
-        inp = _Inputs(prob, J_half)
+        inp = _Inputs(prob, J_half, device_waves)
         o, keep = make_opts(prob, **opt_kw)
         h = _P()
         check(L.etm_plan_create(C.byref(inp.mesh), inp.mats, int(prob.props.shape[0]), C.byref(inp.src), C.byref(o),

@@ -281,7 +281,11 @@ etm_status etm_batch_advance(etm_batch *b, int64_t n, void *stream) {
       if (p->opts.history_stride > 0)
         len = std::min<int64_t>(len, p->opts.history_stride - (p->step % p->opts.history_stride));
     }
-    len = std::max<int64_t>(len, 1);
+    len = std::max<int64_t>(std::min<int64_t>(len, kWaveBlock), 1);
+    // closed-form waves: each variant's sample table covers the segment
+    for (int slot : b->order)
+      if (s == ETM_OK) s = ensure_waves(b->slots[slot], len);
+    if (s != ETM_OK) break;
     if ((s = stage_vars(b, st)) != ETM_OK) break;
     if ((s = run_segment(b, int(len), st)) != ETM_OK) break;
     std::vector<int> old_cur(b->order.size());

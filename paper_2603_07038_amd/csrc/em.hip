@@ -216,10 +216,46 @@ __device__ __forceinline__ int find_port(const DevPorts &P, int64_t key) {
   return -1;
 }
 
+// Value at time t of a closed-form wave (the excitation scheme of Sec. 3.3):
+// a Ricker wavelet, a sine, or a Gaussian pulse train on a carrier, zero
+// outside [t_on, t_off).  Record: kind, n_pulses, amp, t0, width, freq,
+// t_on, t_off, pulse centres.
+__device__ __forceinline__ double wave_value(const double *w, double t) {
+  if (!(t >= w[6] && t < w[7])) return 0.0;
+  const int kind = int(w[0]);
+  const double amp = w[2], t0 = w[3], width = w[4], f = w[5];
+  if (kind == ETM_WAVE_RICKER) {
+    const double u = (t - t0) / width;
+    const double a = u * u;
+    return amp * (1.0 - 2.0 * a) * exp(-a);
+  }
+  if (kind == ETM_WAVE_SINE) return amp * sin(2.0 * M_PI * f * (t - t0));
+  double env = 0.0;
+  const int np = int(w[1]);
+  for (int q = 0; q < np; ++q) {
+    const double u = (t - w[8 + q]) / width;
+    env += exp(-(u * u));
+  }
+  return amp * env * cos(2.0 * M_PI * f * (t - t0));
+}
+
+// Samples s = base .. base + kWaveBlock of every closed-form wave: J at
+// t = (s - 1/2) dt, the same instants as a tabulated wave's samples.
+__global__ __launch_bounds__(256) void wave_sample_kernel(const double *aw, int n, double dt, int64_t base,
+                                                          double *Ja) {
+  const int64_t per = kWaveBlock + 1;
+  const int64_t id = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (id >= int64_t(n) * per) return;
+  const int64_t w = id / per, q = id - w * per;
+  Ja[id] = wave_value(aw + w * kWaveStride, (double(base + q) - 0.5) * dt);
+}
+
 // Source and lumped conductance of port edge q (from find_port) at this step.
 // Port source of EM step n at an edge: jd = dt (J^{n+1/2} - J^{n-1/2}) / eps0
 // (three-level form), jn = dt J^{n+1/2} / eps0 (leapfrog form), and the
-// lumped conductance g (scaled like the a-coefficient).
+// lumped conductance g (scaled like the a-coefficient).  J^{n+1/2} is the
+// sampled value n+1 of a tabulated wave, or of a closed-form wave (sampled on
+// the device, see wave_sample_kernel).
 struct PortTerm {
   double jd, jn, g;
 };
@@ -229,8 +265,17 @@ __device__ __forceinline__ PortTerm port_terms(const DevPorts &P, int q, int64_t
   r.g = P.gs[q];
   const int64_t s1 = step + 1, s0 = step, ns = P.n_samples;
   for (int t = P.start[q]; t < P.start[q + 1]; ++t) {
-    const double *Jw = P.J + int64_t(P.wave[t]) * ns;
-    const double j1 = s1 < ns ? Jw[s1] : 0.0, j0 = s0 < ns ? Jw[s0] : 0.0;
+    const int w = P.wave[t];
+    double j1, j0;
+    if (w < P.n_table) {
+      const double *Jw = P.J + int64_t(w) * ns;
+      j1 = s1 < ns ? Jw[s1] : 0.0;
+      j0 = s0 < ns ? Jw[s0] : 0.0;
+    } else {
+      const double *Jw = P.Ja + int64_t(w - P.n_table) * (kWaveBlock + 1) - P.a_base;
+      j1 = Jw[s1];
+      j0 = Jw[s0];
+    }
     r.jd += P.wt[t] * (j1 - j0);
     r.jn += P.wt[t] * j1;
   }
@@ -426,7 +471,7 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
 
 // Per-node inputs of one plane for the edge update.
 struct YeeNode {
-  float inv[3], a2[3], K[3];
+  float er[3], a2[3], K[3];
   float a2xm, a2ym;  // 2a of the x-edge at i-1 and the y-edge at j-1 (Joule)
   int8_t lo[3];
   uint8_t fl;
@@ -505,7 +550,7 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
     const uint32_t n = uint32_t(kk) * sz + rj;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      c.inv[d] = cf[d * cs + n];
+      c.er[d] = cf[d * cs + n];
       c.a2[d] = cf[(3 + d) * cs + n];
       c.K[d] = Kp ? Kp[d * cs + n] : 0.0f;
       c.lo[d] = elo[d * cs + n];
@@ -594,21 +639,30 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
     const float e0[3] = {c0.x, c0.y, c0.z};
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
-      double inv = double(nd.inv[D]), a2 = double(nd.a2[D]), jn = 0.0;
+      // 1/(er + a) is formed here in FP64 from the stored er and 2a, so the
+      // recurrence is exactly Eq. (2) for the stored pair: two separately
+      // rounded FP32 coefficients would perturb the multiplier (er - a) /
+      // (er + a) of the odd-even mode of good conductors (a ~ 1e4) by ~1e-7
+      // per step.
+      double er = double(nd.er[D]), a2 = double(nd.a2[D]), jn = 0.0;
       if (nd.fl & (1 << D)) {
         const int q = find_port(L.ports, int64_t(D) * g.ntot + n);
         if (q >= 0) {
           const PortTerm pt = port_terms(L.ports, q, step);
-          const double a = 0.5 * a2 + pt.g;
-          inv = rcp64(L.ports.er[q] + a);
-          a2 = 2.0 * a;
+          a2 = 2.0 * (0.5 * a2 + pt.g);
+          er = L.ports.er[q];
           jn = pt.jn;
         }
       }
-      const double dl = -(a2 * double(e0[D]) + cdt * cc[D] + jn - double(nd.K[D])) * inv;
+      const double inv = rcp64(er + 0.5 * a2);
+      // the loss term takes the full e (FP32 part + residual): in a good
+      // conductor 2a / (er + a) ~ 2, so a residual left out of it would come
+      // back into e at FP32 size every step
+      const double ef = e_join(e0[D], nd.lo[D]);
+      const double dl = -(a2 * ef + cdt * cc[D] + jn - double(nd.K[D])) * inv;
       float eh;
       int8_t el;
-      e_split(e_join(e0[D], nd.lo[D]) + dl, eh, el);
+      e_split(ef + dl, eh, el);
       if (pec_d[D]) {
         eh = 0.0f;
         el = 0;
@@ -782,7 +836,7 @@ __global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const 
                           0.5 * (double(a2) - double(a2o)) * (double(ck.e_cur[o]) + double(ck.e_prev[o])));
         }
       }
-      cf[d * cs + n] = T(1.0 / (e + a[d]));
+      cf[d * cs + n] = T(e);
       cf[(3 + d) * cs + n] = T(a2);
     } else {
       cf[d * cs + n] = T(e);
@@ -1035,6 +1089,13 @@ hipError_t launch_em_batched(const BatchVar *vars, const int4 *items, int n_item
   else
     hipLaunchKernelGGL((em_march_batched<float, true>), dim3(n_items), dim3(BX, BY), 0, st, vars, items, n_items,
                        step_ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_wave_sample(const double *aw, int n, double dt, int64_t base, double *Ja, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t total = int64_t(n) * (kWaveBlock + 1);
+  hipLaunchKernelGGL(wave_sample_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, aw, n, dt, base, Ja);
   return hipGetLastError();
 }
 

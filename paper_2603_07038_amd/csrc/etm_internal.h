@@ -52,6 +52,15 @@ struct DevGrid {
   int pec;                        // bit f = face f (-x,+x,-y,+y,-z,+z) is PEC
 };
 
+// A closed-form wave as stored on the device: kind, n_pulses, amp, t0,
+// width, freq, t_on, t_off, pulse centres.  The waves are sampled on the
+// device in blocks of kWaveBlock steps, into a table of samples
+// s = base .. base + kWaveBlock (J at (s - 1/2) dt) that the march kernels
+// read like a tabulated wave; the march kernels themselves carry no
+// transcendental code.
+constexpr int kWaveStride = 16;
+constexpr int kWaveBlock = 1024;
+
 // Port edges, sorted by key = dir * ntot + node.  Entry p has lumped
 // conductance gs[p] (scaled like MC_SIGS) and source terms
 // [start[p], start[p+1]) of (wave, weight * dt / eps0).
@@ -62,8 +71,11 @@ struct DevPorts {
   const int32_t *start;
   const int32_t *wave;
   const double *wt;
-  const double *J;    // [n_waves][n_samples]
+  const double *J;    // [n_table][n_samples]
   int64_t n_samples;
+  const double *Ja;   // closed-form wave n_table + a, sample s: Ja[a * (kWaveBlock + 1) + s - a_base]
+  int64_t a_base;
+  int n_table;        // tabulated waves
   double *er;         // eps_r of each port edge (written by the coefficient kernel)
 };
 
@@ -109,10 +121,13 @@ struct EmLaunch {
   int8_t *elo;            // MIXED: 8-bit residual of e below its FP32 value (updated in place)
 };
 hipError_t launch_em_step(const EmLaunch &L, hipStream_t s);
+// Samples s = base .. base + kWaveBlock of n closed-form waves (records of
+// kWaveStride doubles at aw) into Ja[w * (kWaveBlock + 1) + s - base].
+hipError_t launch_wave_sample(const double *aw, int n, double dt, int64_t base, double *Ja, hipStream_t s);
 // Refresh the per-node coefficients of the own x, y, z edges for the current
 // temperature (FP64 arithmetic, rounded once to the field precision):
 //   FP64:  [eps_r x, y, z, a x, y, z]
-//   mixed: [1/(eps_r + a) x, y, z, 2a x, y, z]
+//   mixed: [eps_r x, y, z, 2a x, y, z]
 // with a = dt sigma(T) / (2 eps0) of the materials (port conductances are
 // added in the march); also the eps_r of every port edge.
 // Mixed path: with K set, also K += (a_new - a_old) (e_cur + e_prev) on every

@@ -119,16 +119,40 @@ etm_status validate_and_copy(etm_plan *p, const etm_mesh *mesh, const etm_materi
   // sources
   p->n_waves = src ? src->n_waves : 0;
   p->n_samples = src ? src->n_samples : 0;
-  if (src && src->n_ports > 0) {
-    if (!src->ports) return fail(ETM_E_INVAL, "null port array");
-    if (src->n_waves < 1 || src->n_samples < 1 || !src->J_half) return fail(ETM_E_INVAL, "ports need sampled waves");
-  }
+  p->n_analytic = src ? src->n_analytic : 0;
+  if (p->n_waves < 0 || p->n_samples < 0 || p->n_analytic < 0) return fail(ETM_E_INVAL, "negative wave counts");
   if (p->n_waves > 0 && p->n_samples > 0) {
     if (!src->J_half) return fail(ETM_E_INVAL, "null J_half");
     p->J.assign(src->J_half, src->J_half + size_t(p->n_waves) * p->n_samples);
   } else {
     p->n_waves = 0;
     p->n_samples = 0;
+  }
+  p->aw.clear();
+  if (p->n_analytic > 0) {
+    if (!src->analytic) return fail(ETM_E_INVAL, "null analytic wave array");
+    for (int w = 0; w < p->n_analytic; ++w) {
+      const etm_wave &a = src->analytic[w];
+      const std::string where = "analytic wave " + std::to_string(w) + ": ";
+      if (a.kind != ETM_WAVE_RICKER && a.kind != ETM_WAVE_SINE && a.kind != ETM_WAVE_GAUSS_TRAIN)
+        return fail(ETM_E_INVAL, where + "unknown kind");
+      const int np = a.kind == ETM_WAVE_GAUSS_TRAIN ? a.n_pulses : 0;
+      if (a.kind == ETM_WAVE_GAUSS_TRAIN && (np < 1 || np > ETM_WAVE_MAX_PULSES))
+        return fail(ETM_E_INVAL, where + "n_pulses must be in 1..8");
+      bool fin = std::isfinite(a.amp) && std::isfinite(a.t0) && std::isfinite(a.width) && std::isfinite(a.freq) &&
+                 std::isfinite(a.t_on) && std::isfinite(a.t_off);
+      for (int q = 0; q < np; ++q) fin = fin && std::isfinite(a.pulse_t[q]);
+      if (!fin) return fail(ETM_E_INVAL, where + "non-finite parameter");
+      if (a.kind != ETM_WAVE_SINE && !(a.width > 0)) return fail(ETM_E_INVAL, where + "width must be > 0");
+      if (!(a.t_on <= a.t_off)) return fail(ETM_E_INVAL, where + "t_on must be <= t_off");
+      const double rec[8] = {double(a.kind), double(np), a.amp, a.t0, a.width, a.freq, a.t_on, a.t_off};
+      p->aw.insert(p->aw.end(), rec, rec + 8);
+      for (int q = 0; q < kWaveStride - 8; ++q) p->aw.push_back(q < np ? a.pulse_t[q] : 0.0);
+    }
+  }
+  if (src && src->n_ports > 0) {
+    if (!src->ports) return fail(ETM_E_INVAL, "null port array");
+    if (p->n_waves + p->n_analytic < 1) return fail(ETM_E_INVAL, "ports need sampled or closed-form waves");
   }
   return ETM_OK;
 }
@@ -313,7 +337,8 @@ etm_status derive(etm_plan *p, const etm_source *src) {
       const int ni = nx + (d != 0), nj = ny + (d != 1), nk = nz + (d != 2);
       if (pt.i < 0 || pt.i >= ni || pt.j < 0 || pt.j >= nj || pt.k < 0 || pt.k >= nk)
         return fail(ETM_E_INVAL, "port " + std::to_string(q) + ": edge outside the mesh");
-      if (pt.wave < 0 || pt.wave >= p->n_waves) return fail(ETM_E_INVAL, "port " + std::to_string(q) + ": wave out of range");
+      if (pt.wave < 0 || pt.wave >= p->n_waves + p->n_analytic)
+        return fail(ETM_E_INVAL, "port " + std::to_string(q) + ": wave out of range");
       if (!std::isfinite(pt.weight) || !(pt.g >= 0)) return fail(ETM_E_INVAL, "port " + std::to_string(q) + ": bad weight/g");
       const int *b = p->opts.em_bc;
       const bool pec = (d != 0 && ((pt.i == 0 && b[0]) || (pt.i == nx && b[1]))) ||
@@ -404,6 +429,8 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   take(p->r_pwt, p->pw_wt.size() * 8);
   take(p->r_per, p->pe_key.size() * 8);
   take(p->r_J, p->J.size() * 8);
+  take(p->r_aw, p->aw.size() * 8);
+  take(p->r_Ja, size_t(p->n_analytic) * (kWaveBlock + 1) * 8);
   take(p->r_probes, p->probes_dev.size() * 8);
   for (int c = 0; c < 6; ++c) take(p->r_coef[c], N * (p->prec == ETM_PREC_FP64 ? 8 : 4));
   if (p->prec == ETM_PREC_FP64) {
@@ -583,7 +610,21 @@ etm_status coef_refresh(etm_plan *p, bool update_k) {
 
 // One EM step e^n -> e^{n+1}; the Joule power of e^n is added to the block
 // sum when it is still pending.
+// Make the device table of closed-form wave samples cover the next `ahead`
+// EM steps (samples step .. step + ahead); refill it from the current step
+// when it does not.  Enqueued on the plan's stream before those steps.
+etm_status ensure_waves(etm_plan *p, int64_t ahead) {
+  if (p->n_analytic == 0) return ETM_OK;
+  if (p->a_base <= p->step && p->step + ahead <= p->a_base + kWaveBlock) return ETM_OK;
+  HIP_TRY(launch_wave_sample(p->ptr<double>(p->r_aw), p->n_analytic, p->dt, p->step, p->ptr<double>(p->r_Ja),
+                             p->stream));
+  p->a_base = p->step;
+  return ETM_OK;
+}
+
 etm_status em_one_step(etm_plan *p) {
+  etm_status st;
+  if ((st = ensure_waves(p, 1)) != ETM_OK) return st;
   EmLaunch L = em_launch_template(p);
   L.acc_joule = p->joule_pending ? 1 : 0;
   em_pointers(p, L);
@@ -1119,10 +1160,12 @@ etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
       (st = up(p->r_pwave, p->pw_wave.data(), p->pw_wave.size() * 4)) ||
       (st = up(p->r_pwt, p->pw_wt.data(), p->pw_wt.size() * 8)) ||
       (st = up(p->r_J, p->J.data(), p->J.size() * 8)) ||
+      (st = up(p->r_aw, p->aw.data(), p->aw.size() * 8)) ||
       (st = up(p->r_probes, p->probes_dev.data(), p->probes_dev.size() * 8)) ||
       (st = up(p->r_mgtab, p->mg_tab.data(), p->mg_tab.size())))
     return st;
   p->bound = true;
+  p->a_base = kNoWaveBlock;
   if ((st = coef_refresh(p, false)) != ETM_OK) return st;
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->step = 0; p->cur = 0; p->th_cur = 0; p->rec = 0; p->n_thermal = 0;
@@ -1330,6 +1373,7 @@ etm_status etm_restore(etm_plan *p, const void *src, size_t bytes) {
   p->sol_t[0] = h.sol_t[0]; p->sol_t[1] = h.sol_t[1];
   p->host_status = ETM_OK;
   p->joule_pending = false;
+  p->a_base = kNoWaveBlock;
   return coef_refresh(p, false);
 }
 

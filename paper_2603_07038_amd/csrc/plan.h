@@ -35,6 +35,9 @@ struct MgHostLevel {
   double c1[kMgDeg] = {}, c2[kMgDeg] = {};
 };
 
+// a_base of a plan whose closed-form wave table holds no valid block
+constexpr int64_t kNoWaveBlock = -(int64_t(1) << 62);
+
 struct etm_plan {
   // ---- inputs (deep copies)
   int nx = 0, ny = 0, nz = 0, n_mat = 0;
@@ -44,6 +47,9 @@ struct etm_plan {
   int n_waves = 0;
   int64_t n_samples = 0;
   std::vector<double> J;
+  int n_analytic = 0;
+  std::vector<double> aw;  // closed-form waves, kWaveStride doubles each
+  int64_t a_base = kNoWaveBlock;  // first sample of the device table of closed-form waves
   etm_opts opts{};
   double dt = 0;
   int prec = ETM_PREC_FP64, R = 1;
@@ -63,7 +69,7 @@ struct etm_plan {
   int64_t hist_cap = 0;
   int hist_cols = 4;
   // ---- workspace regions
-  Region r_geo, r_mtab, r_mat, r_flags, r_fixed, r_pkey, r_pgs, r_pstart, r_pwave, r_pwt, r_J, r_probes, r_per;
+  Region r_geo, r_mtab, r_mat, r_flags, r_fixed, r_pkey, r_pgs, r_pstart, r_pwave, r_pwt, r_J, r_probes, r_per, r_aw, r_Ja;
   Region r_coef[6];     // per-node edge coefficients: eps_r x/y/z, a x/y/z (field precision)
   Region r_e[3][3];     // FP64: three rotating e buffers;  MIXED: [0..1] e sets, [2] unused
   Region r_h[2][3];     // MIXED: face-field sets h^{n-1/2} (x-, y-, z-normal faces)
@@ -136,6 +142,9 @@ struct etm_plan {
     p.wt = ptr<double>(r_pwt);
     p.J = ptr<double>(r_J);
     p.n_samples = n_samples;
+    p.Ja = ptr<double>(r_Ja);
+    p.a_base = a_base;
+    p.n_table = n_waves;
     p.er = ptr<double>(r_per);
     return p;
   }
@@ -153,6 +162,9 @@ struct etm_plan {
 namespace etm {
 EmLaunch em_launch_template(const etm_plan *p);
 etm_status em_one_step(etm_plan *p);
+// Refill the device table of closed-form wave samples if it does not cover the
+// next `ahead` (<= kWaveBlock) EM steps of the plan.
+etm_status ensure_waves(etm_plan *p, int64_t ahead);
 etm_status thermal_one(etm_plan *p);
 etm_status joule_flush(etm_plan *p);
 etm_status coef_refresh(etm_plan *p, bool update_k);

@@ -2,7 +2,8 @@
 
 This module is the only code shared by the FP64 oracle and the HIP library.
 It describes *inputs only*: a rectilinear voxel mesh, one material id per
-cell, a material table, port edges and sampled excitation waveforms.  It holds
+cell, a material table, port edges and excitation waveforms (sampled here,
+or handed to the library as closed-form records).  It holds
 none of the method's arithmetic (no curl-curl, no Joule map, no conduction,
 no elasticity); each side derives everything else on its own.
 
@@ -52,22 +53,55 @@ PROBE_EX, PROBE_EY, PROBE_EZ, PROBE_THETA = 0, 1, 2, 3
 
 # ---------------------------------------------------------------------------
 # Excitation waveforms.  Each returns the waveform value at times t (array);
-# the value is zero for t < 0 (the source is causal).
+# the value is zero for t < 0 (the source is causal), and the windowed kinds
+# are zero outside [t_on, t_off) (t_on >= 0 for every workload here).
 # ---------------------------------------------------------------------------
 @dataclasses.dataclass
 class Wave:
     kind: str                 # "gauss_cos" | "prbs_trap" | "step" | "ramp" | "sine" | "ricker"
+                              # windowed closed forms (also evaluated on the device):
+                              # "ricker_w" | "sine_w" | "gauss_train"
     amp: float                # A/m^2 for current sources, V for voltage ports
     f0: float = 0.0           # carrier / sine frequency [Hz]
-    t0: float = 0.0           # centre [s]
-    tau: float = 0.0          # Gaussian width [s]
+    t0: float = 0.0           # centre / phase reference [s]
+    tau: float = 0.0          # Gaussian or Ricker width [s]
     bitrate: float = 0.0      # [bit/s]
     rise: float = 0.0         # [s]
     bits: Optional[np.ndarray] = None  # NRZ levels 0/1 for prbs_trap
+    t_on: float = 0.0         # windowed kinds: zero outside [t_on, t_off)
+    t_off: float = np.inf
+    centers: Optional[np.ndarray] = None  # gauss_train pulse centres [s]
+
+    WINDOWED = ("ricker_w", "sine_w", "gauss_train")
+
+    def device_params(self) -> dict:
+        """The wave as the library's closed-form wave record (windowed kinds only)."""
+        if self.kind not in self.WINDOWED:
+            raise ValueError(f"wave kind {self.kind} has no closed-form device record")
+        c = np.zeros(8) if self.centers is None else np.asarray(self.centers, dtype=np.float64)
+        return dict(kind={"ricker_w": 1, "sine_w": 2, "gauss_train": 3}[self.kind],
+                    n_pulses=int(len(c)) if self.kind == "gauss_train" else 0, amp=self.amp, t0=self.t0,
+                    width=self.tau, freq=self.f0, t_on=self.t_on, t_off=self.t_off, pulse_t=c)
 
     def __call__(self, t: np.ndarray) -> np.ndarray:
         t = np.asarray(t, dtype=np.float64)
         out = np.zeros_like(t)
+        if self.kind in self.WINDOWED:
+            on = (t >= self.t_on) & (t < self.t_off)
+            tw = t[on]
+            if self.kind == "ricker_w":
+                u = (tw - self.t0) / self.tau
+                a = u * u
+                out[on] = self.amp * (1.0 - 2.0 * a) * np.exp(-a)
+            elif self.kind == "sine_w":
+                out[on] = self.amp * np.sin(2.0 * np.pi * self.f0 * (tw - self.t0))
+            else:
+                env = np.zeros_like(tw)
+                for c in self.centers:
+                    u = (tw - c) / self.tau
+                    env += np.exp(-(u * u))
+                out[on] = self.amp * env * np.cos(2.0 * np.pi * self.f0 * (tw - self.t0))
+            return out
         pos = t >= 0.0
         tp = t[pos]
         if self.kind == "gauss_cos":
@@ -182,6 +216,90 @@ class Problem:
         for w, wave in enumerate(self.waves):
             out[w] = wave(t)
         return out
+
+
+# ---------------------------------------------------------------------------
+# The excitation scheme of Sec. 3.3.  Trace ports form differential pairs
+# (alternating polarity along y) driven by a Ricker "trigger"; bump arrays
+# are fed as Ground-Signal-Ground groups of x-directed current ports, driven
+# by a 5 GHz sine under the logic die and by a 40 GHz carrier under a 3-bit
+# Gaussian pulse train under the HBM die.  Every port draws its own
+# amplitude, width and time shift (deterministic, seeded), so the pairs and
+# groups are not exactly balanced.  Quantities the paper does not give are
+# readings: the Ricker peak frequency (50 GHz: below 1e-3 of its peak at the
+# window edges), the pulse train's slots (three equal slots of the 80-230 ps
+# window, pulses at their centres, 1/e half-width 12 ps) and the bump
+# current density.
+# ---------------------------------------------------------------------------
+TRIGGER_T0, TRIGGER_FP, TRIGGER_WINDOW = 40e-12, 50e9, (20e-12, 60e-12)
+LOGIC_F, LOGIC_WINDOW = 5e9, (0.0, 300e-12)
+BURST_F, BURST_WINDOW, BURST_BITS, BURST_WIDTH = 40e9, (80e-12, 230e-12), 3, 12e-12
+JITTER_AMP, JITTER_WIDTH, JITTER_PHASE = 0.20, 0.10, 10e-12
+BUMP_J0 = 1.0e10   # A/m^2 on a signal bump
+
+
+def paper_jitter(rng) -> tuple:
+    """(amplitude factor, width factor, time shift [s]) of one port."""
+    return (1.0 + rng.uniform(-JITTER_AMP, JITTER_AMP), 1.0 + rng.uniform(-JITTER_WIDTH, JITTER_WIDTH),
+            rng.uniform(-JITTER_PHASE, JITTER_PHASE))
+
+
+def _window(lo, hi, shift, t_origin):
+    # clipped at t = 0: every source is off before the simulation starts (a
+    # window that ended before the time origin becomes the empty [0, 0))
+    return max(lo + shift - t_origin, 0.0), max(hi + shift - t_origin, 0.0)
+
+
+def trigger_wave(amp, jit, t_origin=0.0) -> Wave:
+    fa, fw, sh = jit
+    on, off = _window(*TRIGGER_WINDOW, sh, t_origin)
+    return Wave("ricker_w", amp=amp * fa, t0=TRIGGER_T0 + sh - t_origin, tau=fw / (np.pi * TRIGGER_FP),
+                t_on=on, t_off=off)
+
+
+def logic_wave(amp, jit, t_origin=0.0) -> Wave:
+    fa, _, sh = jit  # a continuous sine has no pulse width to vary
+    on, off = _window(*LOGIC_WINDOW, sh, t_origin)
+    return Wave("sine_w", amp=amp * fa, f0=LOGIC_F, t0=LOGIC_WINDOW[0] + sh - t_origin, t_on=on, t_off=off)
+
+
+def burst_wave(amp, jit, t_origin=0.0) -> Wave:
+    fa, fw, sh = jit
+    on, off = _window(*BURST_WINDOW, sh, t_origin)
+    slot = (BURST_WINDOW[1] - BURST_WINDOW[0]) / BURST_BITS
+    c = BURST_WINDOW[0] + (np.arange(BURST_BITS) + 0.5) * slot + sh - t_origin
+    return Wave("gauss_train", amp=amp * fa, f0=BURST_F, t0=BURST_WINDOW[0] + sh - t_origin,
+                tau=BURST_WIDTH * fw, centers=c, t_on=on, t_off=off)
+
+
+def gsg_role(b: int, n: int) -> float:
+    """Weight of bump b of a column of n along y.  Signal bumps sit at odd b
+    with a ground bump on both sides (b + 1 < n) and carry +1; every ground
+    bump returns -1/2 for each adjacent signal bump, so the unjittered
+    weights of a column sum to zero."""
+    sig = lambda q: 0 <= q < n and q % 2 == 1 and q + 1 < n
+    if sig(b):
+        return 1.0
+    return -0.5 * (sig(b - 1) + sig(b + 1))
+
+
+def gsg_bump_ports(cols, rows, kmid, logic_x, rng, t_origin, waves):
+    """x-directed current ports (3x3 edges through the bump centre at height
+    kmid) on a bump array with centres cols x rows; bumps left of logic_x
+    belong to the logic die, the rest to the HBM die.  Appends one wave per
+    bump to ``waves``; returns the port tuples."""
+    plist = []
+    for ci in cols:
+        for b, cj in enumerate(rows):
+            role = gsg_role(b, len(rows))
+            if role == 0.0:
+                continue
+            wid = len(waves)
+            jit = paper_jitter(rng)
+            waves.append(logic_wave(BUMP_J0, jit, t_origin) if ci < logic_x else burst_wave(BUMP_J0, jit, t_origin))
+            plist += [(d, i, j, k, w, role * wt, g)
+                      for d, i, j, k, w, wt, g in current_port(0, ci - 1, cj - 1, kmid - 1, 2, wid)]
+    return plist
 
 
 def _empty_ports():
@@ -299,7 +417,7 @@ def graded_widths(n: int, dmin: float = 1e-6, extra: float = 4e-6) -> np.ndarray
     return dmin + extra * u * u
 
 
-def config2(seed: int = 2001) -> Problem:
+def config2(seed: int = 2001, excitation: str = "prbs", t_origin: float = 0.0) -> Problem:
     """256x256x64 package slice on a graded rectilinear grid.
 
     x/y widths 1 + 4u^2 um with u = |2(i+1/2)/N - 1| (1 um in the middle,
@@ -313,6 +431,11 @@ def config2(seed: int = 2001) -> Problem:
     one-cell BT gap by a 1 V PRBS-7 trapezoidal burst (5 Gb/s, 20 ps rise)
     through 50 ohm.  PMC on all faces; kinematic mount.  20,000 EM steps,
     R = 200 (100 thermal steps), a PCG solve after every thermal step.
+
+    excitation="paper": the scheme of Sec. 3.3 instead (closed-form waves,
+    one per port, times measured from t_origin): the trace ports become
+    differential pairs driven by the Ricker trigger (+-1 V alternating along
+    y) and the bumps Ground-Signal-Ground groups under the two dies.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     N, nz = 256, 64
@@ -339,6 +462,9 @@ def config2(seed: int = 2001) -> Problem:
         bits = prbs7(int(rng.integers(1, 128)), 8)
         waves.append(Wave("prbs_trap", amp=1.0, bitrate=5e9, rise=20e-12, bits=bits))
         plist += voltage_port(0, 10, j0, kt, 2, t, dx, dy, dz)
+    if excitation == "paper":
+        xrng = np.random.Generator(np.random.PCG64(seed + 7919))
+        waves = [trigger_wave(1.0 if t % 2 == 0 else -1.0, paper_jitter(xrng), t_origin) for t in range(16)]
     # 8x8 microbumps, 6x6 cells each, through the underfill layer.
     k0, k1 = bounds[2]
     for bj in range(8):
@@ -346,6 +472,9 @@ def config2(seed: int = 2001) -> Problem:
         for bi in range(8):
             ci = int(round((bi + 0.5) * N / 8))
             mat[k0:k1, cj - 3:cj + 3, ci - 3:ci + 3] = CU
+    if excitation == "paper":
+        bumps = [int(round((b + 0.5) * N / 8)) for b in range(8)]
+        plist += gsg_bump_ports(bumps, bumps, (k0 + k1) // 2, N // 2, xrng, t_origin, waves)
     # TSV grid in the interposer.
     k0, k1 = bounds[3]
     xn = np.concatenate([[0.0], np.cumsum(dx)])
@@ -364,7 +493,9 @@ def config2(seed: int = 2001) -> Problem:
     probes = np.array([[PROBE_EX, 10, int(round(0.5 * N / 16)), kt],
                        [PROBE_EX, 64, int(round(0.5 * N / 16)), kt],
                        [PROBE_THETA, 64, int(round(0.5 * N / 16)), kt]], dtype=np.int64)
-    return Problem(name="slice256x256x64_graded", dx=dx, dy=dy, dz=dz, mat=mat,
+    if excitation not in ("prbs", "paper"):
+        raise ValueError(f"unknown excitation {excitation}")
+    return Problem(name="slice256x256x64_graded" + ("_paperexc" if excitation == "paper" else ""), dx=dx, dy=dy, dz=dz, mat=mat,
                    props=package_materials(), waves=waves, em_bc=(PMC,) * 6,
                    mech_bc=MECH_KINEMATIC, n_em_steps=20000, em_per_thermal=200,
                    mech_every_thermal=1, cg_rtol=1e-8, probes=probes, history_stride=1000,
@@ -377,14 +508,21 @@ def config2(seed: int = 2001) -> Problem:
 def package(nx: int, ny: int, nz: int, seed: int, *, bump_pitch_um: float = 16.0,
             bump_cells: int = 8, trace_width: int = 1, trace_pitch: int = 2,
             n_trace_layers: int = 8, max_traces: Optional[int] = None, n_bits: int = 256,
-            steps_per_bit: int = 16, em_per_thermal: int = 256, name: str = "package") -> Problem:
+            steps_per_bit: int = 16, em_per_thermal: int = 256, name: str = "package",
+            excitation: str = "prbs", t_origin: float = 0.0) -> Problem:
     """Uniform 1 um package voxelisation, layer thicknesses scaled from the
     128-cell stack: Cu ground (2) / BT (30) / Cu bumps in underfill (16) /
     Si interposer with TSVs under the bumps (32) / polyimide RDL with
     ``n_trace_layers`` routing layers of traces alternating x/y (32) / two Si
     dies with an air gap (12) / air (4).  Every trace is driven across a
     one-cell gap near its start by its own seeded PRBS-7 burst (1 V through
-    50 ohm, rise = a quarter bit)."""
+    50 ohm, rise = a quarter bit).
+
+    excitation="paper": the scheme of Sec. 3.3 instead (closed-form waves,
+    one per port, times measured from t_origin): the traces become
+    differential pairs driven by the Ricker trigger (+-1 V alternating in
+    trace order) and every bump column a Ground-Signal-Ground line, under
+    the logic die (left half) or the HBM die (right half)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     um = 1e-6
     dx, dy, dz = np.full(nx, um), np.full(ny, um), np.full(nz, um)
@@ -439,6 +577,14 @@ def package(nx: int, ny: int, nz: int, seed: int, *, bump_pitch_um: float = 16.0
                 mat[kk:kk + w, 2:ny - 2, s:s + w] = CU
                 mat[kk:kk + w, 4, s:s + w] = POLYIMIDE
                 plist += voltage_port(1, s, 4, kk, w, wid, dx, dy, dz)
+    if excitation == "paper":
+        xrng = np.random.Generator(np.random.PCG64(seed + 7919))
+        waves = [trigger_wave(1.0 if t % 2 == 0 else -1.0, paper_jitter(xrng), t_origin) for t in range(len(waves))]
+        cols = list(range(p // 2, nx - bc // 2, p))
+        rows = list(range(p // 2, ny - bc // 2, p))
+        plist += gsg_bump_ports(cols, rows, (k0 + k1) // 2, nx // 2, xrng, t_origin, waves)
+    elif excitation != "prbs":
+        raise ValueError(f"unknown excitation {excitation}")
     # dies with a gap
     d0, d1 = bounds[5]
     g0, g1 = int(0.48 * nx), int(0.52 * nx)
@@ -468,14 +614,16 @@ def bind_step_timing(p: Problem, dt: float) -> Problem:
     return p
 
 
-def config3(seed: int = 3001) -> Problem:
+def config3(seed: int = 3001, excitation: str = "prbs", t_origin: float = 0.0) -> Problem:
     """1024x1024x128 full-scale one-GPU package: 6 material classes, 64x64
     bumps of 8x8 cells at 16-cell pitch, 8 RDL routing layers x 512 traces
     (width 1, pitch 2, alternating x/y) = 4096 traces, each with a 256-bit
-    PRBS-7 burst at 16 steps per bit (4096 EM steps), R = 256."""
+    PRBS-7 burst at 16 steps per bit (4096 EM steps), R = 256.
+    excitation="paper": the Sec. 3.3 scheme on the same geometry."""
     return package(1024, 1024, 128, seed, bump_pitch_um=16, bump_cells=8, trace_width=1,
                    trace_pitch=2, n_trace_layers=8, n_bits=256, steps_per_bit=16,
-                   em_per_thermal=256, name="package1024x1024x128")
+                   em_per_thermal=256, name="package1024x1024x128" + ("_paperexc" if excitation == "paper" else ""),
+                   excitation=excitation, t_origin=t_origin)
 
 
 def config4_variant(v: int) -> Problem:
