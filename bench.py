@@ -16,6 +16,9 @@ Joule / CG refinement); the same blocks are timed on the FP64 path.
 Beside the headline, the same JSON line carries:
   fullscale  the 1024x1024x128 package (134 M cells): EM march rate and its
              HBM roofline fraction, mixed and FP64;
+  excitation the same package under the excitation scheme of Sec. 3.3 (52,640
+             port edges, one closed-form wave per port sampled on the
+             device): EM march rate, mixed;
   batch      64 design variants of uneven size (64x64x32 .. 192x192x48,
              2048 EM steps + a mechanical solve each): one batched mixed run
              against 64 sequential FP64 runs and a batched FP64 run, with
@@ -26,7 +29,7 @@ Beside the headline, the same JSON line carries:
              server: p50/p99 latency and designs/hour, mixed and FP64.
 
     python bench.py [--steps K] [--warmup W] [--precision mixed|fp64] [--no-fp64] [--no-cpu]
-                    [--legs coupled,fullscale,batch,serve] [--serve-requests N] [--serve-rate R]
+                    [--legs coupled,fullscale,excitation,batch,serve] [--serve-requests N] [--serve-rate R]
 """
 from __future__ import annotations
 
@@ -62,7 +65,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--legs", default="coupled,fullscale,batch,serve")
+    ap.add_argument("--legs", default="coupled,fullscale,excitation,batch,serve")
     ap.add_argument("--batch-variants", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-rate", type=float, default=2.0)
@@ -205,6 +208,38 @@ def fullscale_leg(steps=48, warmup=8):
     return out
 
 
+def excitation_leg(steps=256, warmup=8, t_origin=95e-12):
+    """EM march of the 1024x1024x128 package under the excitation scheme of
+    Sec. 3.3 (one closed-form wave per port, sampled on the device in blocks
+    of steps), mixed precision, in a window where the 5 GHz sine and the
+    40 GHz burst are on; the march rate against the tabulated-PRBS package
+    of the fullscale leg, and the host table the device sampling avoids for
+    the scheme's 300 ps window."""
+    import torch
+    import workloads as W
+    import paper_2603_07038_amd as etm
+    prob = W.config3(excitation="paper", t_origin=t_origin)
+    prob.history_stride = 0
+    dt = etm.cfl_dt(prob)
+    plan = etm.Plan(prob, None, dt=dt, precision=etm.ETM_PREC_MIXED, n_steps=steps + warmup, history=False,
+                    device_waves=True)
+    plan.advance(warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(plan.stream)
+    plan.advance(steps)
+    e1.record(plan.stream)
+    info = plan.sync()
+    t = e0.elapsed_time(e1) / 1e3 / steps
+    window_steps = int(round(300e-12 / dt))
+    out = {"workload": prob.name, "cells": prob.n_cells, "port_edges": prob.n_ports, "waves": len(prob.waves),
+           "t_origin_s": t_origin, "em_steps": steps, "march_mcell_steps_per_s": round(prob.n_cells / t / 1e6, 1),
+           "em_step_us": round(t * 1e6, 1), "theta_max_K": info["theta_max"],
+           "host_table_bytes_avoided_300ps": len(prob.waves) * (window_steps + 1) * 8}
+    del plan
+    torch.cuda.synchronize()
+    return out
+
+
 def batch_leg(n_variants):
     """The 64-variant batch: batched mixed vs sequential FP64 (and batched FP64)."""
     import numpy as np
@@ -336,6 +371,8 @@ def main():
     extra = {}
     if "fullscale" in legs:
         extra["fullscale"] = fullscale_leg()
+    if "excitation" in legs:
+        extra["excitation"] = excitation_leg()
     if "batch" in legs:
         extra["batch"] = batch_leg(a.batch_variants)
     if "serve" in legs:
