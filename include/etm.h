@@ -166,7 +166,7 @@ typedef struct {
                                    (solved with a dense inverse; default 800, range 3..4000) */
     int32_t mg_degree[2];       /* multigrid: Chebyshev smoothing steps before and after the coarse
                                    correction on the finest level and on the coarser levels
-                                   (0 = default 2; range 1..4) */
+                                   (0 = default: 3 on the finest level, 2 below; range 1..4) */
 } etm_opts;
 
 /* What etm_sync reports. */

@@ -100,7 +100,7 @@ etm_status validate_and_copy(etm_plan *p, const etm_mesh *mesh, const etm_materi
   if (p->opts.mg_coarse_dofs < 3 || p->opts.mg_coarse_dofs > 4000)
     return fail(ETM_E_INVAL, "mg_coarse_dofs must be 0 (default) or 3..4000");
   for (int q = 0; q < 2; ++q) {
-    if (opts->mg_degree[q] == 0) p->opts.mg_degree[q] = 2;
+    if (opts->mg_degree[q] == 0) p->opts.mg_degree[q] = q == 0 ? 3 : 2;
     if (p->opts.mg_degree[q] < 1 || p->opts.mg_degree[q] > kMgDeg)
       return fail(ETM_E_INVAL, "mg_degree entries must be 0 (default) or 1..4");
   }
@@ -1078,7 +1078,8 @@ etm_status etm_opts_default(etm_opts *o) {
   o->cg_rtol = 1e-8;
   o->mech_precond = ETM_PRECOND_MG;
   o->mg_coarse_dofs = 800;
-  o->mg_degree[0] = o->mg_degree[1] = 2;
+  o->mg_degree[0] = 3;
+  o->mg_degree[1] = 2;
   return ETM_OK;
 }
 
