@@ -249,6 +249,12 @@ hipError_t launch_cg_apply_alpha(const MechGrid &M, const CgVecs<T> &v, double *
 constexpr int kMgMaxLevels = 16;
 constexpr int kMgDeg = 4;   // most Chebyshev steps before (and after) the coarse correction
 constexpr int kMgUpper = 14;  // stored stencil blocks: the centre and the 13 offsets after it
+// Entry (r, c) of stored stencil block q of node `node` on a level of n nodes:
+// the three entries of a block row are contiguous, so a wave reads a row of
+// 64 consecutive nodes as one 768-byte span.
+inline __host__ __device__ int64_t stencil_idx(int q, int r, int c, int64_t n, int64_t node) {
+  return ((int64_t(q) * 3 + r) * n + node) * 3 + c;
+}
 
 template <typename T>
 struct V3 {
@@ -265,7 +271,8 @@ template <typename T>
 struct MgLevel {
   int nx, ny, nz;          // cells
   int64_t sy, sz, n;       // node strides; n = entries per component of the level's vectors
-  const T *A;              // [kMgUpper*9][n] stencil blocks (coarse levels; level 0 when it is the coarsest)
+  const T *A;              // stencil blocks (coarse levels; level 0 when it is the coarsest): row r of block q
+                           // at node n is A[((q * 3 + r) * n_nodes + n) * 3 + (0..2)] (see stencil_idx)
   T *Dinv;                 // [6][n] inverse nodal diagonal block (xx, yy, zz, xy, yz, xz); dead rows zero
   uint8_t *dead;           // per node: bit c = DOF c outside the space (fixed, or no stiffness)
   V3<T> xa, xb, d, b;      // smoother iterates, Chebyshev direction, right-hand side (coarse levels)

@@ -55,18 +55,18 @@ template <typename T>
 __device__ __forceinline__ void stencil_block(const MgLevel<T> &L, int64_t n, int o, double B[9]) {
   const int64_t N = L.n;
   if (o >= 13) {
-    const T *P = L.A + int64_t(o - 13) * 9 * N + n;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) B[e] = double(P[e * N]);
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) B[r * 3 + c] = double(L.A[stencil_idx(o - 13, r, c, N, n)]);
   } else {
     int ox, oy, oz;
     off3(o, ox, oy, oz);
     const int64_t m = n + ox + oy * L.sy + oz * L.sz;
-    const T *P = L.A + int64_t(13 - o) * 9 * N + m;
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) B[r * 3 + c] = double(P[(c * 3 + r) * N]);
+      for (int c = 0; c < 3; ++c) B[r * 3 + c] = double(L.A[stencil_idx(13 - o, c, r, N, m)]);
   }
 }
 
@@ -84,16 +84,19 @@ __device__ __forceinline__ void stencil_apply(const MgLevel<T> &L, int i, int j,
     if (ii < 0 || ii > L.nx || jj < 0 || jj > L.ny || kk < 0 || kk > L.nz) continue;
     const int64_t m = n + ox + oy * L.sy + oz * L.sz;
     const T x0 = x.c[0][m], x1 = x.c[1][m], x2 = x.c[2][m];
+    // rows of block q at node p (each three contiguous entries)
+    const int q = o >= 13 ? o - 13 : 13 - o;
+    const int64_t p = o >= 13 ? n : m;
+    const T *R0 = L.A + stencil_idx(q, 0, 0, N, p), *R1 = L.A + stencil_idx(q, 1, 0, N, p),
+            *R2 = L.A + stencil_idx(q, 2, 0, N, p);
     if (o >= 13) {
-      const T *B = L.A + int64_t(o - 13) * 9 * N + n;
-      y0 += B[0] * x0 + B[N] * x1 + B[2 * N] * x2;
-      y1 += B[3 * N] * x0 + B[4 * N] * x1 + B[5 * N] * x2;
-      y2 += B[6 * N] * x0 + B[7 * N] * x1 + B[8 * N] * x2;
-    } else {
-      const T *B = L.A + int64_t(13 - o) * 9 * N + m;
-      y0 += B[0] * x0 + B[3 * N] * x1 + B[6 * N] * x2;
-      y1 += B[N] * x0 + B[4 * N] * x1 + B[7 * N] * x2;
-      y2 += B[2 * N] * x0 + B[5 * N] * x1 + B[8 * N] * x2;
+      y0 += R0[0] * x0 + R0[1] * x1 + R0[2] * x2;
+      y1 += R1[0] * x0 + R1[1] * x1 + R1[2] * x2;
+      y2 += R2[0] * x0 + R2[1] * x1 + R2[2] * x2;
+    } else {  // the transpose of the block stored at the lower neighbour
+      y0 += R0[0] * x0 + R1[0] * x1 + R2[0] * x2;
+      y1 += R0[1] * x0 + R1[1] * x1 + R2[1] * x2;
+      y2 += R0[2] * x0 + R1[2] * x1 + R2[2] * x2;
     }
   }
   y[0] = y0; y[1] = y1; y[2] = y2;
@@ -307,7 +310,7 @@ __global__ __launch_bounds__(256) void mg_galerkin0_kernel(MechGrid M, const uin
   }
   const int64_t node = int64_t(K) * csz + int64_t(J) * csy + I;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) A[(int64_t(q) * 9 + e) * cn + node] = T(acc[e]);
+  for (int e = 0; e < 9; ++e) A[stencil_idx(q, e / 3, e % 3, cn, node)] = T(acc[e]);
 }
 
 // Coarse stencil of level l+1 from the stencil of level l (F).
@@ -369,7 +372,7 @@ __global__ __launch_bounds__(256) void mg_galerkin_kernel(MgLevel<T> F, int cnx,
   }
   const int64_t node = int64_t(K) * csz + int64_t(J) * csy + I;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) A[(int64_t(q) * 9 + e) * cn + node] = T(acc[e]);
+  for (int e = 0; e < 9; ++e) A[stencil_idx(q, e / 3, e % 3, cn, node)] = T(acc[e]);
 }
 
 // Deterministic start vector of the power iteration (dead DOFs zero).

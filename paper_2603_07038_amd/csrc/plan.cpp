@@ -843,10 +843,10 @@ void coarse_inverse(const MgHostLevel &H, const std::vector<T> &A, const std::ve
             const int64_t nb = n + ox + oy * H.sy + oz * H.sz;
             double B[9];
             if (o >= 13) {
-              for (int e = 0; e < 9; ++e) B[e] = double(A[(size_t(o - 13) * 9 + e) * N + n]);
+              for (int e = 0; e < 9; ++e) B[e] = double(A[stencil_idx(o - 13, e / 3, e % 3, N, n)]);
             } else {
               for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c) B[r * 3 + c] = double(A[(size_t(13 - o) * 9 + c * 3 + r) * N + nb]);
+                for (int c = 0; c < 3; ++c) B[r * 3 + c] = double(A[stencil_idx(13 - o, c, r, N, nb)]);
             }
             for (int r = 0; r < 3; ++r) {
               const int rr = col[n * 3 + r];
