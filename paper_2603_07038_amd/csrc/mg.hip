@@ -391,12 +391,26 @@ __global__ __launch_bounds__(256) void mg_start_kernel(MgLevel<T> L, V3<T> v) {
   }
 }
 
-// w = Dinv A (scale * v); partial sums of |w|^2.
+// Power iteration for lambda_max(Dinv A).  With u = scale * v (unit length
+// after the first step), y = A u and z = Dinv y, the kernel stores w = z and
+// sums z.y, u.y and |z|^2.  Dinv A is self-adjoint in the A inner product,
+// so z.y / u.y = <u, Dinv A u>_A / <u, u>_A is a Rayleigh quotient: a lower
+// bound of lambda_max whose error falls as (lambda_2 / lambda_1)^(2k), twice
+// the rate of the norm ratio |z|.
+__device__ __forceinline__ void power_sums(const double u[3], const double y[3], const double z[3], double red[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    red[0] += z[c] * y[c];
+    red[1] += u[c] * y[c];
+    red[2] += z[c] * z[c];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void mg_power_kernel(MgLevel<T> L, V3<T> v, V3<T> w,
                                                        const double *scale, double *partials) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  double ww = 0.0;
+  double red[3] = {0.0, 0.0, 0.0};
   if (i <= L.nx && j <= L.ny) {
     const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
     T y[3];
@@ -409,20 +423,22 @@ __global__ __launch_bounds__(256) void mg_power_kernel(MgLevel<T> L, V3<T> v, V3
     const T z1 = s * (d01 * y[0] + d11 * y[1] + d12 * y[2]);
     const T z2 = s * (d02 * y[0] + d12 * y[1] + d22 * y[2]);
     w.c[0][n] = z0; w.c[1][n] = z1; w.c[2][n] = z2;
-    ww = double(z0) * double(z0) + double(z1) * double(z1) + double(z2) * double(z2);
+    const double u[3] = {double(s) * double(v.c[0][n]), double(s) * double(v.c[1][n]), double(s) * double(v.c[2][n])};
+    const double ys[3] = {double(s) * double(y[0]), double(s) * double(y[1]), double(s) * double(y[2])};
+    const double zd[3] = {double(z0), double(z1), double(z2)};
+    power_sums(u, ys, zd, red);
   }
-  const double sv[1] = {ww};
   const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  block_sums<1>(sv, partials + b * kRedWidth);
+  block_sums<3>(red, partials + b * kRedWidth);
 }
 
 __global__ void mg_power_finalize(const double *part, int64_t nb, double *lam, double *scale) {
-  __shared__ double out[1];
-  sum_partials<1>(part, nb, out);
+  __shared__ double out[3];
+  sum_partials<3>(part, nb, out);
   if (threadIdx.x == 0) {
-    const double s = sqrt(out[0]);
-    *lam = s;
-    *scale = s > 0.0 ? 1.0 / s : 0.0;
+    const double zn = sqrt(out[2]);
+    *lam = out[1] > 0.0 ? out[0] / out[1] : 0.0;
+    *scale = zn > 0.0 ? 1.0 / zn : 0.0;
   }
 }
 
@@ -664,16 +680,21 @@ struct EpiPower0 {
     dinv_load<T>(L, n, q.D);
     return q;
   }
-  __device__ void operator()(int64_t n, const T y[3], const T *, const Pre &q, double *red) const {
+  // the power step of mg_power_kernel on the matrix-free level (sums z.y, u.y, |z|^2)
+  __device__ void operator()(int64_t n, const T y[3], const T xc[3], const Pre &q, double *red) const {
     T z[3];
     dinv_apply<T>(q.D, y, z);
     const T s = T(*scale);
+    double u[3], ys[3], zd[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       z[c] *= s;
       w.c[c][n] = z[c];
-      red[0] += double(z[c]) * double(z[c]);
+      u[c] = double(s) * double(xc[c]);
+      ys[c] = double(s) * double(y[c]);
+      zd[c] = double(z[c]);
     }
+    power_sums(u, ys, zd, red);
   }
 };
 
@@ -892,7 +913,7 @@ hipError_t launch_mg_power(const MgDev<T> &G, int l, int iters, double *partials
   const int64_t nb = l == 0 ? cell_blocks(G.M.g, cell_kchunk(G.M.g)) : lblocks(L);
   for (int it = 0; it < iters; ++it) {
     if (l == 0) {
-      hipError_t e = launch_hex8<T, 1>(G.M, v.c, EpiPower0<T>{L, w, (const double *)G.scale}, partials, nullptr, s);
+      hipError_t e = launch_hex8<T, 3>(G.M, v.c, EpiPower0<T>{L, w, (const double *)G.scale}, partials, nullptr, s);
       if (e != hipSuccess) return e;
     } else {
       hipLaunchKernelGGL((mg_power_kernel<T>), lgrid(L), dim3(BX, BY), 0, s, L, v, w, (const double *)G.scale,
