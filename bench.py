@@ -15,7 +15,10 @@ Joule / CG refinement); the same blocks are timed on the FP64 path.
 
 Beside the headline, the same JSON line carries:
   fullscale  the 1024x1024x128 package (134 M cells): EM march rate and its
-             HBM roofline fraction, mixed and FP64;
+             HBM roofline fraction, mixed and FP64, and mixed with the
+             two-step slab wavefront over 8 z-slabs (temporal blocking);
+  temporal_blocking  the slice's EM march per step with the two-step slab
+             wavefront over 3 and 8 z-slabs against one launch per step;
   excitation the same package under the excitation scheme of Sec. 3.3 (52,640
              port edges, one closed-form wave per port sampled on the
              device): EM march rate, mixed;
@@ -29,7 +32,7 @@ Beside the headline, the same JSON line carries:
              server: p50/p99 latency and designs/hour, mixed and FP64.
 
     python bench.py [--steps K] [--warmup W] [--precision mixed|fp64] [--no-fp64] [--no-cpu]
-                    [--legs coupled,fullscale,excitation,batch,serve] [--serve-requests N] [--serve-rate R]
+                    [--legs coupled,fullscale,temporal,excitation,batch,serve] [--serve-requests N] [--serve-rate R]
 """
 from __future__ import annotations
 
@@ -65,17 +68,19 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--legs", default="coupled,fullscale,excitation,batch,serve")
+    ap.add_argument("--legs", default="coupled,fullscale,temporal,excitation,batch,serve")
     ap.add_argument("--batch-variants", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-rate", type=float, default=2.0)
-    ap.add_argument("--probe", choices=["em", "em-fp64", "copy"], default=None,
-                    help="short runs for hardware-counter profiles: 20 EM steps of the workload, or a plain "
-                         "2 GiB device copy (the calibration kernel for FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--probe", choices=["em", "em-fp64", "em-pair", "copy"], default=None,
+                    help="short runs for hardware-counter profiles: 20 EM steps of the workload (em-pair: as "
+                         "10 two-step slab wavefronts over --probe-slabs z-slabs), or a plain 2 GiB device copy "
+                         "(the calibration kernel for FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--probe-slabs", type=int, default=3)
     return ap.parse_args()
 
 
-def probe(kind):
+def probe(kind, slabs=3):
     import torch
     if kind == "copy":
         x = torch.ones(1 << 28, dtype=torch.float64, device="cuda")  # 2 GiB
@@ -94,10 +99,12 @@ def probe(kind):
     dt = etm.cfl_dt(prob)
     J = prob.sample_J_half(dt, 64)
     prec = etm.ETM_PREC_FP64 if kind == "em-fp64" else etm.ETM_PREC_MIXED
-    plan = etm.Plan(prob, J, dt=dt, precision=prec, n_steps=64, history=False)
+    plan = etm.Plan(prob, J, dt=dt, precision=prec, n_steps=64, history=False,
+                    em_slabs=slabs if kind == "em-pair" else 0)
     plan.advance(20)
     plan.sync()
-    print(json.dumps({"probe": kind, "workload": prob.name, "cells": prob.n_cells, "em_steps": 20}))
+    print(json.dumps({"probe": kind, "workload": prob.name, "cells": prob.n_cells, "em_steps": 20,
+                      "em_slabs": slabs if kind == "em-pair" else 0}))
 
 
 PROFILE_EM = {"mixed": "profiles/em_march_slice256x256x64_mixed.md"}
@@ -190,8 +197,9 @@ def fullscale_leg(steps=48, warmup=8):
     dt = etm.cfl_dt(prob)
     J = prob.sample_J_half(dt, steps + warmup + 2)
     out = {"workload": prob.name, "cells": prob.n_cells}
-    for name, prec in (("mixed", etm.ETM_PREC_MIXED), ("fp64", etm.ETM_PREC_FP64)):
-        plan = etm.Plan(prob, J, dt=dt, precision=prec, n_steps=steps + warmup + 2, history=False)
+    for name, prec, slabs in (("mixed", etm.ETM_PREC_MIXED, 0), ("fp64", etm.ETM_PREC_FP64, 0),
+                              ("mixed_em_slabs8", etm.ETM_PREC_MIXED, 8)):
+        plan = etm.Plan(prob, J, dt=dt, precision=prec, n_steps=steps + warmup + 2, history=False, em_slabs=slabs)
         plan.advance(warmup)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(plan.stream)
@@ -199,10 +207,39 @@ def fullscale_leg(steps=48, warmup=8):
         e1.record(plan.stream)
         plan.sync()
         t = e0.elapsed_time(e1) / 1e3 / steps
-        bpc = BYTES_PER_CELL_STEP[name]
+        bpc = BYTES_PER_CELL_STEP[name.split("_")[0]]
         gbs = bpc * prob.n_cells / t / 1e9
         out[name] = {"march_mcell_steps_per_s": round(prob.n_cells / t / 1e6, 1), "em_kernel_us": round(t * 1e6, 1),
                      "achieved_GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        del plan
+        torch.cuda.synchronize()
+    return out
+
+
+def temporal_leg(steps=100, warmup=10, slabs=(0, 3, 8)):
+    """EM march of the 256x256x64 slice (mixed) with the two-step slab
+    wavefront (em_slabs = S) against one launch per step (S = 0); the
+    fullscale leg runs the package with S = 8."""
+    import torch
+    import workloads as W
+    import paper_2603_07038_amd as etm
+    prob = W.config2()
+    prob.mech_every_thermal = 0
+    prob.em_per_thermal = 100000
+    prob.history_stride = 0
+    dt = etm.cfl_dt(prob)
+    J = prob.sample_J_half(dt, steps + warmup + 2)
+    out = {"workload": prob.name, "cells": prob.n_cells, "em_steps": steps, "us_per_step": {}}
+    for S in slabs:
+        plan = etm.Plan(prob, J, dt=dt, precision=etm.ETM_PREC_MIXED, n_steps=steps + warmup + 2, history=False,
+                        em_slabs=S)
+        plan.advance(warmup)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(plan.stream)
+        plan.advance(steps)
+        e1.record(plan.stream)
+        plan.sync()
+        out["us_per_step"][str(S)] = round(e0.elapsed_time(e1) * 1e3 / steps, 2)
         del plan
         torch.cuda.synchronize()
     return out
@@ -351,7 +388,7 @@ def cpu_baseline(prob, dt, J, budget_s):
 def main():
     a = parse()
     if a.probe:
-        probe(a.probe)
+        probe(a.probe, a.probe_slabs)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -371,6 +408,8 @@ def main():
     extra = {}
     if "fullscale" in legs:
         extra["fullscale"] = fullscale_leg()
+    if "temporal" in legs:
+        extra["temporal_blocking"] = temporal_leg()
     if "excitation" in legs:
         extra["excitation"] = excitation_leg()
     if "batch" in legs:

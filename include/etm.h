@@ -167,6 +167,13 @@ typedef struct {
     int32_t mg_degree[2];       /* multigrid: Chebyshev smoothing steps before and after the coarse
                                    correction on the finest level and on the coarser levels
                                    (0 = default: 3 on the finest level, 2 below; range 1..4) */
+    int32_t em_slabs;           /* temporal blocking of the EM march: 0 or 1 = one launch per step;
+                                   S >= 2 = two steps at a time as a wavefront over S z-slabs, the
+                                   second step of a slab running right after the first has finished
+                                   the slab and its neighbours, so it finds them in the on-chip caches.
+                                   Results are bitwise those of one launch per step.  Pairs never
+                                   straddle a thermal step or a history record.  Range 0..64. */
+    int32_t reserved;
 } etm_opts;
 
 /* What etm_sync reports. */

@@ -721,6 +721,30 @@ __global__ __launch_bounds__(256) void em_march_kernel(EmLaunch L, EmPtrs<T> p, 
   march_tile<T, YEE>(L, p, L.step, tx, ty, kc, kchunk, acc_joule);
 }
 
+// ---- two steps as a wavefront over z-slabs (temporal blocking) -------------
+// One launch runs the tiles of two z-ranges of chunks: blocks [0, nA) make
+// step n on chunks [kcA, kcA + nkcA) with pointer set pa, blocks [nA, nb)
+// make step n + 1 on chunks [kcB, kcB + nkcB) with pb.  The host orders the
+// launches so that the n + 1 range runs only after the step-n tiles it
+// reads (its own slab and the planes next to it) are complete and after
+// every step-n tile that reads the planes it overwrites; see
+// launch_em_pair_schedule.  Each tile computes exactly what it computes in
+// a one-step launch, so the two steps are bitwise those of two launches.
+template <typename T, bool YEE>
+__global__ __launch_bounds__(256) void em_march_pair_kernel(EmLaunch L, EmPtrs<T> pa, EmPtrs<T> pb, int ntx, int nty,
+                                                            int kcA, int nkcA, int kcB, int nkcB, int kchunk,
+                                                            int acc_a) {
+  const int cols = ntx * nty, nA = cols * nkcA, nb = nA + cols * nkcB;
+  const int b = xcd_remap(blockIdx.x, nb);
+  const bool second = b >= nA;
+  const int r = second ? b - nA : b;
+  const int tx = r % ntx, ty = (r / ntx) % nty, kc = (second ? kcB : kcA) + r / cols;
+  if (second)
+    march_tile<T, YEE>(L, pb, L.step + 1, tx, ty, kc, kchunk, 1);
+  else
+    march_tile<T, YEE>(L, pa, L.step, tx, ty, kc, kchunk, acc_a);
+}
+
 // ---- batched: one launch walks the (variant, tile) list of all variants ----
 // Item = (variant, tile x, tile y, z chunk).  The step offset s is read from
 // device memory so that a captured chunk of steps can be replayed.
@@ -1078,6 +1102,53 @@ hipError_t launch_em_step(const EmLaunch &L, hipStream_t s) {
     hipLaunchKernelGGL((em_march_kernel<float, true>), dim3(nb), block, 0, s, L, p, ntx, nty, nkc, kc, L.acc_joule);
   }
   return hipGetLastError();
+}
+
+// Steps n and n + 1 (La: pointers and Joule flag of step n; Lb: pointers of
+// step n + 1) as a wavefront over n_slabs z-slabs of whole chunks.  Launch t
+// runs step n on slab t + 1 (slabs 0 and 1 in launch 0) and step n + 1 on
+// slab t - 1 (slabs S - 2 and S - 1 in the last launch), so step n + 1 on a
+// slab follows step n on that slab and its two neighbours, and no step-n
+// tile still to run reads a plane step n + 1 overwrites (slab s + 2 reads
+// down to the last plane of slab s + 1 only).  S launches for the two steps.
+hipError_t launch_em_pair_schedule(const EmLaunch &La, const EmLaunch &Lb, int n_slabs, hipStream_t s) {
+  int ntx, nty, nkc;
+  const int kc = La.kchunk > 0 ? La.kchunk : em_kchunk(La.g, La.precision);
+  em_tiles(La.g, La.precision, kc, &ntx, &nty, &nkc);
+  const int S = std::max(2, std::min(n_slabs, nkc));
+  auto first = [&](int q) { return int(int64_t(q) * nkc / S); };  // first chunk of slab q
+  const dim3 block(BX, BY, 1);
+  for (int t = 0; t < S; ++t) {
+    // step-n slabs [a0, a1), step-(n + 1) slabs [b0, b1) of this launch
+    int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    if (t == 0) {
+      a1 = 2;
+    } else if (t == S - 1) {
+      b0 = S - 2;
+      b1 = S;
+    } else {
+      a0 = t + 1; a1 = t + 2;
+      b0 = t - 1; b1 = t;
+    }
+    const int kcA = a0 < a1 ? first(a0) : 0, nkcA = a0 < a1 ? first(a1) - first(a0) : 0;
+    const int kcB = b0 < b1 ? first(b0) : 0, nkcB = b0 < b1 ? first(b1) - first(b0) : 0;
+    const int nb = ntx * nty * (nkcA + nkcB);
+    if (nb == 0) continue;
+    if (La.precision == ETM_PREC_FP64) {
+      EmPtrs<double> pa{(const double *)La.e0[0], (const double *)La.e1[0], (double *)La.out0[0], nullptr};
+      EmPtrs<double> pb{(const double *)Lb.e0[0], (const double *)Lb.e1[0], (double *)Lb.out0[0], nullptr};
+      hipLaunchKernelGGL((em_march_pair_kernel<double, false>), dim3(nb), block, 0, s, La, pa, pb, ntx, nty, kcA, nkcA,
+                         kcB, nkcB, kc, La.acc_joule);
+    } else {
+      EmPtrs<float> pa{(const float *)La.e0[0], (const float *)La.e1[0], (float *)La.out0[0], (float *)La.out1[0]};
+      EmPtrs<float> pb{(const float *)Lb.e0[0], (const float *)Lb.e1[0], (float *)Lb.out0[0], (float *)Lb.out1[0]};
+      hipLaunchKernelGGL((em_march_pair_kernel<float, true>), dim3(nb), block, 0, s, La, pa, pb, ntx, nty, kcA, nkcA,
+                         kcB, nkcB, kc, La.acc_joule);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_em_batched(const BatchVar *vars, const int4 *items, int n_items, const int64_t *step_ctr,

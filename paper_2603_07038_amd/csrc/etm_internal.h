@@ -121,6 +121,8 @@ struct EmLaunch {
   int8_t *elo;            // MIXED: 8-bit residual of e below its FP32 value (updated in place)
 };
 hipError_t launch_em_step(const EmLaunch &L, hipStream_t s);
+// Steps n and n + 1 as a wavefront over z-slabs (La: step n, Lb: step n + 1).
+hipError_t launch_em_pair_schedule(const EmLaunch &La, const EmLaunch &Lb, int n_slabs, hipStream_t s);
 // Samples s = base .. base + kWaveBlock of n closed-form waves (records of
 // kWaveStride doubles at aw) into Ja[w * (kWaveBlock + 1) + s - base].
 hipError_t launch_wave_sample(const double *aw, int n, double dt, int64_t base, double *Ja, hipStream_t s);

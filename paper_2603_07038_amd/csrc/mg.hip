@@ -18,9 +18,12 @@
 //     blocks: the centre and the 13 offsets after it are stored, the other
 //     13 blocks are the transposes stored at the neighbour;
 //   * smoothing is Chebyshev on the nodal 3x3-block Jacobi operator, with the
-//     top of the spectrum from a few power iterations; the same polynomial
-//     before and after the coarse correction keeps the V-cycle symmetric, so
-//     it is a valid CG preconditioner;
+//     top of the spectrum bounded from below by a Rayleigh quotient after a
+//     fixed number of power steps; the same polynomial before and after the
+//     coarse correction keeps the V-cycle symmetric, so it is a valid CG
+//     preconditioner while the interval covers the spectrum;
+//   * stencil blocks are stored row by row: the three entries of a block
+//     row are contiguous, so a node's block is three 12-byte loads;
 //   * the coarsest level is solved exactly with a dense inverse built on the
 //     host once per plan.
 // Level 0 is applied matrix free (the same HEX8 apply as the CG operator).

@@ -104,6 +104,7 @@ etm_status validate_and_copy(etm_plan *p, const etm_mesh *mesh, const etm_materi
     if (p->opts.mg_degree[q] < 1 || p->opts.mg_degree[q] > kMgDeg)
       return fail(ETM_E_INVAL, "mg_degree entries must be 0 (default) or 1..4");
   }
+  if (opts->em_slabs < 0 || opts->em_slabs > 64) return fail(ETM_E_INVAL, "em_slabs must be 0..64");
   p->prec = opts->precision;
   p->R = opts->em_per_thermal;
   // time step
@@ -631,6 +632,31 @@ etm_status em_one_step(etm_plan *p) {
   HIP_TRY(launch_em_step(L, p->stream));
   p->cur = p->prec == ETM_PREC_FP64 ? (p->cur + 1) % 3 : 1 - p->cur;
   p->step++;
+  p->joule_pending = true;
+  return ETM_OK;
+}
+
+// Index of the state buffer that held the field one step before the current
+// one (after a step or a pair of steps).
+static int previous_state(const etm_plan *p) {
+  return p->prec == ETM_PREC_FP64 ? (p->cur + 2) % 3 : 1 - p->cur;
+}
+
+// Steps n and n + 1 as a wavefront over z-slabs (temporal blocking); the
+// state afterwards is that of two em_one_step calls, bitwise.
+etm_status em_two_steps(etm_plan *p) {
+  etm_status st;
+  if ((st = ensure_waves(p, 2)) != ETM_OK) return st;
+  EmLaunch La = em_launch_template(p);
+  La.acc_joule = p->joule_pending ? 1 : 0;
+  em_pointers(p, La);
+  const int c0 = p->cur;
+  p->cur = p->prec == ETM_PREC_FP64 ? (c0 + 1) % 3 : 1 - c0;
+  EmLaunch Lb = La;
+  em_pointers(p, Lb);
+  p->cur = p->prec == ETM_PREC_FP64 ? (c0 + 2) % 3 : c0;
+  HIP_TRY(launch_em_pair_schedule(La, Lb, p->opts.em_slabs, p->stream));
+  p->step += 2;
   p->joule_pending = true;
   return ETM_OK;
 }
@@ -1192,9 +1218,14 @@ etm_status etm_advance(etm_plan *p, int64_t n) {
   if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
   if (n < 0) return fail(ETM_E_INVAL, "negative step count");
   etm_status st;
-  for (int64_t q = 0; q < n; ++q) {
-    const int old = p->cur;
-    if ((st = em_one_step(p)) != ETM_OK) return st;
+  const int64_t hs = p->opts.history_stride;
+  for (int64_t q = 0; q < n;) {
+    // a pair of steps when enabled and nothing is due after the first one
+    const bool pair = p->opts.em_slabs >= 2 && n - q >= 2 && (p->step + 1) % p->R != 0 &&
+                      !(hs > 0 && (p->step + 1) % hs == 0);
+    if ((st = pair ? em_two_steps(p) : em_one_step(p)) != ETM_OK) return st;
+    q += pair ? 2 : 1;
+    const int old = previous_state(p);
     if (p->step % p->R == 0) {
       if ((st = thermal_one(p)) != ETM_OK) return st;
       if (p->opts.mech_every_thermal > 0 && p->n_thermal % p->opts.mech_every_thermal == 0) {

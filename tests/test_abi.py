@@ -111,6 +111,11 @@ def test_validation_errors():
     assert _create(p, J, mg_coarse_dofs=2)[0] == etm.ETM_E_INVAL
     assert _create(p, J, mg_coarse_dofs=5000)[0] == etm.ETM_E_INVAL
     assert _create(p, J, mech_precond=etm.ETM_PRECOND_JACOBI)[0] == etm.ETM_OK
+    assert _create(p, J, mg_degree=(C.c_int32 * 2)(5, 2))[0] == etm.ETM_E_INVAL
+    # temporal blocking of the EM march: 0..64 z-slabs
+    assert _create(p, J, em_slabs=-1)[0] == etm.ETM_E_INVAL
+    assert _create(p, J, em_slabs=65)[0] == etm.ETM_E_INVAL
+    assert _create(p, J, em_slabs=8)[0] == etm.ETM_OK
 
 
 def test_calls_before_bind_are_state_errors():
