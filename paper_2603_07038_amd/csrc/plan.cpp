@@ -1336,6 +1336,7 @@ etm_status etm_read_history(const etm_plan *p, double *dst, size_t bytes, int64_
   return ETM_OK;
 }
 
+extern "C++" {  // helpers of the checkpoint entry points (C++ linkage)
 namespace {
 struct CkptHeader {
   uint64_t magic;
@@ -1365,6 +1366,7 @@ std::vector<const Region *> state_regions(const etm_plan *p) {
   return r;
 }
 }  // namespace
+}  // extern "C++"
 
 etm_status etm_checkpoint_size(const etm_plan *p, size_t *bytes) {
   if (!p || !bytes) return fail(ETM_E_INVAL, "null argument");
