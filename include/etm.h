@@ -173,7 +173,13 @@ typedef struct {
                                    the slab and its neighbours, so it finds them in the on-chip caches.
                                    Results are bitwise those of one launch per step.  Pairs never
                                    straddle a thermal step or a history record.  Range 0..64. */
-    int32_t reserved;
+    int32_t mech_overlap;       /* 1 (default) = a scheduled mechanical solve runs on a side stream while
+                                   the EM steps that follow it in the same etm_advance call (up to the
+                                   next thermal step or history record) run on the plan's stream; the
+                                   solve reads only the temperature of its own thermal step and the
+                                   march never reads the displacement, so results are bitwise those of
+                                   the serial order.  0 = serial.  The plan's stream waits for the
+                                   solve before any later work. */
 } etm_opts;
 
 /* What etm_sync reports. */

@@ -70,7 +70,7 @@ class etm_opts(C.Structure):
                 ("cg_rtol", C.c_double), ("history_stride", C.c_int32), ("n_probes", C.c_int32),
                 ("probes", C.POINTER(C.c_int64)), ("history_cap", C.c_int64), ("n_em_steps_hint", C.c_int64),
                 ("mech_precond", C.c_int32), ("mg_coarse_dofs", C.c_int32), ("mg_degree", C.c_int32 * 2),
-                ("em_slabs", C.c_int32), ("reserved", C.c_int32)]
+                ("em_slabs", C.c_int32), ("mech_overlap", C.c_int32)]
 
 
 class etm_run_info(C.Structure):

@@ -105,6 +105,7 @@ etm_status validate_and_copy(etm_plan *p, const etm_mesh *mesh, const etm_materi
       return fail(ETM_E_INVAL, "mg_degree entries must be 0 (default) or 1..4");
   }
   if (opts->em_slabs < 0 || opts->em_slabs > 64) return fail(ETM_E_INVAL, "em_slabs must be 0..64");
+  if (opts->mech_overlap != 0 && opts->mech_overlap != 1) return fail(ETM_E_INVAL, "mech_overlap must be 0 or 1");
   p->prec = opts->precision;
   p->R = opts->em_per_thermal;
   // time step
@@ -1114,6 +1115,7 @@ etm_status etm_opts_default(etm_opts *o) {
   o->mg_coarse_dofs = 800;
   o->mg_degree[0] = 3;
   o->mg_degree[1] = 2;
+  o->mech_overlap = 1;
   return ETM_OK;
 }
 
@@ -1176,6 +1178,9 @@ etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(ETM_E_INVAL, "workspace must be 256-byte aligned");
   p->ws = static_cast<char *>(ws);
   p->stream = static_cast<hipStream_t>(stream);
+  if (!p->mstream) HIP_TRY(hipStreamCreateWithFlags(&p->mstream, hipStreamNonBlocking));
+  if (!p->ev_main) HIP_TRY(hipEventCreateWithFlags(&p->ev_main, hipEventDisableTiming));
+  if (!p->ev_mech) HIP_TRY(hipEventCreateWithFlags(&p->ev_mech, hipEventDisableTiming));
   if (!p->sc_host) HIP_TRY(hipHostMalloc((void **)&p->sc_host, sizeof(DevScalars), hipHostMallocDefault));
   std::memset(p->sc_host, 0, sizeof(DevScalars));
   HIP_TRY(launch_fill(p->ws, int64_t(p->footprint), p->stream));
@@ -1219,22 +1224,56 @@ etm_status etm_advance(etm_plan *p, int64_t n) {
   if (n < 0) return fail(ETM_E_INVAL, "negative step count");
   etm_status st;
   const int64_t hs = p->opts.history_stride;
-  for (int64_t q = 0; q < n;) {
-    // a pair of steps when enabled and nothing is due after the first one
-    const bool pair = p->opts.em_slabs >= 2 && n - q >= 2 && (p->step + 1) % p->R != 0 &&
-                      !(hs > 0 && (p->step + 1) % hs == 0);
-    if ((st = pair ? em_two_steps(p) : em_one_step(p)) != ETM_OK) return st;
-    q += pair ? 2 : 1;
+  auto history_due = [&](int64_t s) { return hs > 0 && s % hs == 0; };
+  int64_t q = 0;
+  // One EM step, or a pair when enabled, at most `limit` steps, and nothing
+  // is due after the first of the two.
+  auto march = [&](int64_t limit) -> etm_status {
+    const bool pair = p->opts.em_slabs >= 2 && limit >= 2 && (p->step + 1) % p->R != 0 && !history_due(p->step + 1);
+    const etm_status s2 = pair ? em_two_steps(p) : em_one_step(p);
+    if (s2 == ETM_OK) q += pair ? 2 : 1;
+    return s2;
+  };
+  while (q < n) {
+    if ((st = march(n - q)) != ETM_OK) return st;
     const int old = previous_state(p);
+    bool hist = history_due(p->step);
     if (p->step % p->R == 0) {
       if ((st = thermal_one(p)) != ETM_OK) return st;
       if (p->opts.mech_every_thermal > 0 && p->n_thermal % p->opts.mech_every_thermal == 0) {
-        st = mech_solve_impl(p);
+        if (p->opts.mech_overlap) {
+          // The record of this step first (it does not read the mechanics,
+          // and the steps enqueued next replace the state it reads).
+          if (hist && (st = diag_record(p, old)) != ETM_OK) return st;
+          hist = false;
+          HIP_TRY(hipEventRecord(p->ev_main, p->stream));
+          // Enqueue the EM steps that need nothing else before them: short of
+          // the next thermal step and the next history record, within this
+          // call.  They read the edge coefficients and the fields, never the
+          // temperature buffer the solve reads or anything the solve writes.
+          for (;;) {
+            const int64_t s_th = (p->step / p->R + 1) * p->R;
+            const int64_t s_h = hs > 0 ? (p->step / hs + 1) * hs : INT64_MAX;
+            const int64_t allowed = std::min<int64_t>(n - q, std::min(s_th, s_h) - p->step - 1);
+            if (allowed <= 0) break;
+            if ((st = march(allowed)) != ETM_OK) return st;
+          }
+          // The solve on the side stream, after the thermal step; the plan's
+          // stream waits for it before any later work.
+          HIP_TRY(hipStreamWaitEvent(p->mstream, p->ev_main, 0));
+          hipStream_t main_stream = p->stream;
+          p->stream = p->mstream;
+          st = mech_solve_impl(p);
+          p->stream = main_stream;
+          HIP_TRY(hipEventRecord(p->ev_mech, p->mstream));
+          HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_mech, 0));
+        } else {
+          st = mech_solve_impl(p);
+        }
         if (st != ETM_OK && st != ETM_E_NOCONV) return st;
       }
     }
-    if (p->opts.history_stride > 0 && p->step % p->opts.history_stride == 0)
-      if ((st = diag_record(p, old)) != ETM_OK) return st;
+    if (hist && (st = diag_record(p, old)) != ETM_OK) return st;
   }
   return joule_flush(p);
 }
@@ -1421,6 +1460,10 @@ etm_status etm_restore(etm_plan *p, const void *src, size_t bytes) {
 
 void etm_plan_destroy(etm_plan *p) {
   if (!p) return;
+  if (p->mstream) (void)hipStreamSynchronize(p->mstream);
+  if (p->ev_main) (void)hipEventDestroy(p->ev_main);
+  if (p->ev_mech) (void)hipEventDestroy(p->ev_mech);
+  if (p->mstream) (void)hipStreamDestroy(p->mstream);
   if (p->sc_host) (void)hipHostFree(p->sc_host);
   delete p;
 }

@@ -89,6 +89,10 @@ struct etm_plan {
   // ---- bound state
   char *ws = nullptr;
   hipStream_t stream = nullptr;
+  // side stream of overlapped mechanical solves, and the events that order
+  // it against the plan's stream (created at the first bind)
+  hipStream_t mstream = nullptr;
+  hipEvent_t ev_main = nullptr, ev_mech = nullptr;
   bool bound = false;
   DevScalars *sc_host = nullptr;  // pinned
   int64_t step = 0;

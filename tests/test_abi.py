@@ -116,6 +116,8 @@ def test_validation_errors():
     assert _create(p, J, em_slabs=-1)[0] == etm.ETM_E_INVAL
     assert _create(p, J, em_slabs=65)[0] == etm.ETM_E_INVAL
     assert _create(p, J, em_slabs=8)[0] == etm.ETM_OK
+    assert _create(p, J, mech_overlap=2)[0] == etm.ETM_E_INVAL
+    assert _create(p, J, mech_overlap=0)[0] == etm.ETM_OK
 
 
 def test_calls_before_bind_are_state_errors():
