@@ -1078,13 +1078,17 @@ void em_tiles(const DevGrid &g, int precision, int kchunk, int *ntx, int *nty, i
 }
 
 int em_kchunk(const DevGrid &g, int precision) {
-  // Enough blocks to fill 256 CUs several times over, with chunks long
-  // enough that the two extra planes staged per chunk stay cheap.
+  // Planes per block, from sweeps on gfx950 in both precisions: on the
+  // 256x256x64 slice 6 planes beat 4, 8, 10, 12 and 16 (124 against 131 us
+  // per mixed step at 8), on the 1024x1024x128 package 12 beat 8, 16, 24
+  // and 32 (3.27 against 3.48 ms at 16).  Long chunks on many columns, short
+  // ones otherwise, and shorter still (down to 4) while a launch would have
+  // fewer than 2048 blocks to spread over the 256 CUs.
   int ntx, nty, nkc;
   em_tiles(g, precision, 1, &ntx, &nty, &nkc);
   const int64_t cols = int64_t(ntx) * nty;
-  int kc = 16;
-  while (kc > 4 && cols * ((g.nz + 1 + kc - 1) / kc) < 2048) kc /= 2;
+  int kc = cols * ((g.nz + 1 + 11) / 12) >= 8192 ? 12 : 6;
+  while (kc > 4 && cols * ((g.nz + 1 + kc - 1) / kc) < 2048) kc = std::max(4, kc - 2);
   return kc;
 }
 
