@@ -2,8 +2,8 @@
 
     python -m paper_2603_07038_amd.tune [--out FILE] [--classes 15-24] [--steps 64]
 
-The batched march works on 64x4-node column tiles cut into z-chunks of
-``kchunk`` node planes.  Short chunks give more work items (better load
+The batched march works on tiles of 4 node rows (64 nodes wide in FP64, 62
+in mixed precision) cut into z-chunks of ``kchunk`` node planes.  Short chunks give more work items (better load
 balance when few variants are attached) but stage two extra planes per
 chunk; long chunks amortise the halo.  For each size class (floor of log2 of
 the cell count, the key the batch uses) a package variant of that size is
@@ -22,7 +22,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tune_gfx950.json")
-CANDIDATES = (2, 4, 8, 16, 32, 64)
+CANDIDATES = (2, 4, 6, 8, 12, 16, 24, 32)
 
 
 def class_problem(c: int):
