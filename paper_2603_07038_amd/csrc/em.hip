@@ -477,16 +477,16 @@ struct YeeNode {
   uint8_t fl;
 };
 
-// One wave per x-row, no barriers.  A wave owns WX = 62 consecutive nodes
-// of one row (j, k) and marches up its z-chunk on its own: lane L holds node i = WX * ts - 1 + L, so lanes 0 and
-// 63 overlap the neighbouring segments and every x-neighbour a face or the
-// Joule gather needs is one lane away (whole-wave DPP shifts).  The rows
-// j - 1 and j + 1 are read directly (their own waves read the same lines,
-// so they are L2 hits), the faces of row j - 1 that the edge update needs are
-// recomputed in-wave with the same expression their owner uses, and the y
-// factors of the row are wave-uniform.  No LDS and no barriers: each wave's
-// loads for the next plane are in flight while it computes the current one,
-// and its neighbours on the SIMD fill the gaps.
+// One wave per run of nodes, no barriers.  A wave owns WX = 62 consecutive
+// nodes of a plane numbered x fastest (a run may cross the end of a row) and
+// marches up its z-chunk on its own: lanes 0 and 63 overlap the neighbouring
+// runs, so every x-neighbour a face or the Joule gather needs is one lane
+// away (whole-wave DPP shifts).  The rows j - 1 and j + 1 of each lane's node
+// are read directly (their own waves read the same lines, so they are L2
+// hits), and the faces of row j - 1 that the edge update needs are
+// recomputed in-wave with the same expression their owner uses.  No LDS and
+// no barriers: each wave's loads for the next plane are in flight while it
+// computes the current one, and its neighbours on the SIMD fill the gaps.
 constexpr int WX = 62;
 
 __device__ __forceinline__ float lane_next(float v) {  // value of lane + 1 (0 past the last lane)
@@ -506,17 +506,28 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const uint32_t sy = uint32_t(g.sy), sz = uint32_t(g.sz), cs = g.cs;
   const int lane = threadIdx.x;
-  const int j = tr * BY + __builtin_amdgcn_readfirstlane(int(threadIdx.y));  // wave-uniform row
-  if (j > ny) return;
+  (void)tr;  // one launch row of blocks per z-chunk (em_tiles)
+  // Wave w owns the nodes t = WX w .. WX w + WX - 1 of the plane numbered x
+  // fastest (t = j (nx + 1) + i); lane L holds t = WX w - 1 + L, so lanes 0
+  // and 63 overlap the neighbouring waves and every x-neighbour is one lane
+  // away.  A wave may run across the end of a row (the lane after node
+  // (nx, j) holds (0, j + 1)): every term that would read across -- the faces
+  // at i = nx, and through them the faces and x-edge at i - 1 of node 0 --
+  // does not exist and is masked, so short rows leave no lanes idle.
+  const int nx1 = nx + 1, nplane = nx1 * (ny + 1);
+  const int w = ts * BY + __builtin_amdgcn_readfirstlane(int(threadIdx.y));
+  if (WX * w >= nplane) return;  // the whole wave is past the plane
   const Geo G(g.geo, nx, ny, nz);
   const float *cf = static_cast<const float *>(L.coef);
   const float *Kp = L.K;
   int8_t *elo = L.elo;
   const double cdt = L.cdt;
-  const int i = WX * ts - 1 + lane;
-  const bool inb = i >= 0 && i <= nx;                       // node exists
-  const bool own = lane >= 1 && lane <= WX && i <= nx;      // node updated by this lane
-  const int ic = min(max(i, 0), nx);
+  const int t = WX * w - 1 + lane;
+  const bool inb = t >= 0 && t < nplane;                    // node exists
+  const int tc = min(max(t, 0), nplane - 1);
+  const int j = tc / nx1, ic = tc - j * nx1;                // (clamped for lanes off the plane)
+  const int i = inb ? ic : -1;
+  const bool own = lane >= 1 && lane <= WX && inb;          // node updated by this lane
   const int k0 = kc * kchunk, k1 = min(k0 + kchunk, nz + 1);
   const bool jm_ok = j > 0, jp_ok = j < ny;                 // rows j - 1, j + 1 exist
   const uint32_t rj = uint32_t(j) * sy + uint32_t(ic);
@@ -531,7 +542,7 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
     return RowE{ld(p.e, kk, r, ok), ld(p.e + cs, kk, r, ok), ld(p.e + 2 * cs, kk, r, ok)};
   };
 
-  // per-lane x factors, per-wave y factors
+  // per-lane x and y factors
   const double dxi = G.idx[min(ic, nx - 1)], dhx = G.ihx[ic];
   const double ax[2] = {G.axl[ic], G.axh[ic]};
   const double dyj = G.idy[min(j, ny - 1)], dym = G.idy[max(j - 1, 0)], dhy = G.ihy[j];
@@ -1071,9 +1082,16 @@ __global__ void fill_kernel(uint32_t *dst, int64_t n_words) {
 }  // namespace
 
 void em_tiles(const DevGrid &g, int precision, int kchunk, int *ntx, int *nty, int *nkc) {
-  const int wx = precision == ETM_PREC_MIXED ? WX : BX;  // nodes a block owns along x
-  *ntx = (g.nx + 1 + wx - 1) / wx;
-  *nty = (g.ny + 1 + BY - 1) / BY;
+  if (precision == ETM_PREC_MIXED) {
+    // BY waves of WX nodes of the x-fastest plane per block, one row of blocks
+    const int64_t plane = int64_t(g.nx + 1) * (g.ny + 1), per = int64_t(WX) * BY;
+    *ntx = int((plane + per - 1) / per);
+    *nty = 1;
+  } else {
+    // BX x BY node tiles
+    *ntx = (g.nx + 1 + BX - 1) / BX;
+    *nty = (g.ny + 1 + BY - 1) / BY;
+  }
   *nkc = (g.nz + 1 + kchunk - 1) / kchunk;
 }
 

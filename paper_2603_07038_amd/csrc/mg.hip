@@ -38,6 +38,17 @@ namespace {
 
 using namespace mech;
 
+// Node (i, j) of the thread in a plane of (nx + 1) x (ny + 1) nodes: the
+// plane's nodes are numbered x fastest and cut into blocks of BX * BY
+// threads, so the coarse levels' short rows (129, 65, 33 nodes) fill the
+// waves instead of leaving up to half of each 64-wide row tile idle.
+// Threads past the end of the plane get j > ny.
+__device__ __forceinline__ void plane_node(int nx, int &i, int &j) {
+  const int t = int(blockIdx.x) * (BX * BY) + int(threadIdx.y) * BX + int(threadIdx.x);
+  j = t / (nx + 1);
+  i = t - j * (nx + 1);
+}
+
 // Offsets of the 27-point stencil: o = (oz+1)*9 + (oy+1)*3 + (ox+1);
 // o = 13 is the centre and 26 - o is the opposite offset.
 __device__ __forceinline__ void off3(int o, int &ox, int &oy, int &oz) {
@@ -149,7 +160,9 @@ __device__ __forceinline__ void inv3_live(const double Bin[9], uint8_t dead, dou
 template <typename T>
 __global__ __launch_bounds__(256) void mg_diag0_kernel(MechGrid M, T *Dinv, int64_t dn, uint8_t *dead) {
   const DevGrid &g = M.g;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  int i, j;
+  plane_node(g.nx, i, j);
+  const int k = blockIdx.z;
   if (i > g.nx || j > g.ny) return;
   const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
   double B[9] = {};
@@ -185,7 +198,9 @@ __global__ __launch_bounds__(256) void mg_diag0_kernel(MechGrid M, T *Dinv, int6
 // Nodal blocks of a stencil level: centre block, dead mask, inverse.
 template <typename T>
 __global__ __launch_bounds__(256) void mg_diag_kernel(MgLevel<T> L) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  int i, j;
+  plane_node(L.nx, i, j);
+  const int k = blockIdx.z;
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   double B[9];
@@ -381,7 +396,9 @@ __global__ __launch_bounds__(256) void mg_galerkin_kernel(MgLevel<T> F, int cnx,
 // Deterministic start vector of the power iteration (dead DOFs zero).
 template <typename T>
 __global__ __launch_bounds__(256) void mg_start_kernel(MgLevel<T> L, V3<T> v) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  int i, j;
+  plane_node(L.nx, i, j);
+  const int k = blockIdx.z;
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   const uint8_t dd = L.dead[n];
@@ -412,7 +429,9 @@ __device__ __forceinline__ void power_sums(const double u[3], const double y[3],
 template <typename T>
 __global__ __launch_bounds__(256) void mg_power_kernel(MgLevel<T> L, V3<T> v, V3<T> w,
                                                        const double *scale, double *partials) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  int i, j;
+  plane_node(L.nx, i, j);
+  const int k = blockIdx.z;
   double red[3] = {0.0, 0.0, 0.0};
   if (i <= L.nx && j <= L.ny) {
     const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
@@ -470,7 +489,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void mg_smooth_kernel(MgLevel<T> L, V3<T> b, V3<T> xin, V3<T> xout,
                                                         T c1, T c2, int first, const DevScalars *sc) {
   if (sc && sc->done) return;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  int i, j;
+  plane_node(L.nx, i, j);
+  const int k = blockIdx.z;
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   T r[3];
@@ -500,7 +521,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void mg_resid_kernel(MgLevel<T> L, V3<T> b, V3<T> x, V3<T> r,
                                                        const DevScalars *sc) {
   if (sc && sc->done) return;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  int i, j;
+  plane_node(L.nx, i, j);
+  const int k = blockIdx.z;
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   T y[3];
@@ -516,7 +539,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void mg_restrict_kernel(MgLevel<T> F, V3<T> r, MgLevel<T> C, int smooth, T c2,
                                                           const DevScalars *sc) {
   if (sc && sc->done) return;
-  const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y, K = blockIdx.z;
+  int I, J;
+  plane_node(C.nx, I, J);
+  const int K = blockIdx.z;
   if (I > C.nx || J > C.ny) return;
   const int fi0 = F.ax[0].cpos[I], fj0 = F.ax[1].cpos[J], fk0 = F.ax[2].cpos[K];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -551,7 +576,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void mg_prolong_kernel(MgLevel<T> F, V3<T> x, MgLevel<T> C, V3<T> xc,
                                                          const DevScalars *sc) {
   if (sc && sc->done) return;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  int i, j;
+  plane_node(F.nx, i, j);
+  const int k = blockIdx.z;
   if (i > F.nx || j > F.ny) return;
   const int64_t n = int64_t(k) * F.sz + int64_t(j) * F.sy + i;
   const int lx = F.ax[0].lo[i], ly = F.ax[1].lo[j], lz = F.ax[2].lo[k];
@@ -578,7 +605,9 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(MgLevel<T> F, V3<T> x, 
 template <typename T>
 __global__ __launch_bounds__(256) void mg_zero_kernel(MgLevel<T> L, V3<T> x, const DevScalars *sc) {
   if (sc && sc->done) return;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  int i, j;
+  plane_node(L.nx, i, j);
+  const int k = blockIdx.z;
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   x.c[0][n] = T(0); x.c[1][n] = T(0); x.c[2][n] = T(0);
@@ -737,7 +766,9 @@ __global__ __launch_bounds__(256) void cgmg_dot_kernel(MechGrid M, CgVecs<T> v, 
                                                        double *partials) {
   if (sc->done) return;
   const DevGrid &g = M.g;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  int i, j;
+  plane_node(g.nx, i, j);
+  const int k = blockIdx.z;
   double rz = 0.0;
   if (i <= g.nx && j <= g.ny) {
     const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
@@ -814,9 +845,11 @@ __global__ void cgmg_rr_finalize(const double *part, int64_t nb, DevScalars *sc)
 
 inline int flat_blocks(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024))); }
 
+// One thread per node of a plane (plane_node), blockIdx.z the plane.
 template <typename T>
 inline dim3 lgrid(const MgLevel<T> &L) {
-  return dim3((L.nx + 1 + BX - 1) / BX, (L.ny + 1 + BY - 1) / BY, L.nz + 1);
+  const int64_t plane = int64_t(L.nx + 1) * (L.ny + 1);
+  return dim3(unsigned((plane + BX * BY - 1) / (BX * BY)), 1, L.nz + 1);
 }
 
 template <typename T>
