@@ -405,7 +405,7 @@ def main():
         probe(a.probe, a.probe_slabs)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     import workloads as W
