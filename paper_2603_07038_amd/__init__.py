@@ -341,7 +341,7 @@ class Plan:
         check(load().etm_restore(self.h, buf.ctypes.data, buf.nbytes))
 
 
-def solve_all(plans, workers=4):
+def solve_all(plans, workers=8):
     """Mechanical solves of several bound plans at once.  Each solve runs from
     a worker thread on its plan's own stream (the library releases the GIL
     while it waits), so the small solves of a batch overlap on the GPU.
