@@ -75,10 +75,11 @@ def parse():
     ap.add_argument("--batch-variants", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-rate", type=float, default=2.0)
-    ap.add_argument("--probe", choices=["em", "em-fp64", "em-pair", "copy"], default=None,
+    ap.add_argument("--probe", choices=["em", "em-fp64", "em-pair", "mech", "copy"], default=None,
                     help="short runs for hardware-counter profiles: 20 EM steps of the workload (em-pair: as "
-                         "10 two-step slab wavefronts over --probe-slabs z-slabs), or a plain 2 GiB device copy "
-                         "(the calibration kernel for FETCH_SIZE / WRITE_SIZE)")
+                         "10 two-step slab wavefronts over --probe-slabs z-slabs), two coupling blocks with their "
+                         "mechanical solves (mech), or a plain 2 GiB device copy (the calibration kernel for "
+                         "FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--probe-slabs", type=int, default=3)
     return ap.parse_args()
 
@@ -97,6 +98,16 @@ def probe(kind, slabs=3):
     import workloads as W
     import paper_2603_07038_amd as etm
     prob = W.config2()
+    if kind == "mech":
+        dt = etm.cfl_dt(prob)
+        R = prob.em_per_thermal
+        J = prob.sample_J_half(dt, 2 * R + 2)
+        plan = etm.Plan(prob, J, dt=dt, precision=etm.ETM_PREC_MIXED, n_steps=2 * R + 2, history=False)
+        plan.advance(2 * R)
+        info = plan.sync()
+        print(json.dumps({"probe": kind, "workload": prob.name, "cells": prob.n_cells, "em_steps": 2 * R,
+                          "mech_solves": info["n_solves"], "cg_iters_total": info["cg_iters_total"]}))
+        return
     prob.mech_every_thermal = 0
     prob.em_per_thermal = 256  # 20 steps: no thermal step inside the probe
     dt = etm.cfl_dt(prob)
@@ -238,6 +249,16 @@ def temporal_leg(steps=100, warmup=10, slabs=(0, 3, 8)):
     import workloads as W
     import paper_2603_07038_amd as etm
     prob = W.config2()
+    if kind == "mech":
+        dt = etm.cfl_dt(prob)
+        R = prob.em_per_thermal
+        J = prob.sample_J_half(dt, 2 * R + 2)
+        plan = etm.Plan(prob, J, dt=dt, precision=etm.ETM_PREC_MIXED, n_steps=2 * R + 2, history=False)
+        plan.advance(2 * R)
+        info = plan.sync()
+        print(json.dumps({"probe": kind, "workload": prob.name, "cells": prob.n_cells, "em_steps": 2 * R,
+                          "mech_solves": info["n_solves"], "cg_iters_total": info["cg_iters_total"]}))
+        return
     prob.mech_every_thermal = 0
     prob.em_per_thermal = 100000
     prob.history_stride = 0
