@@ -726,13 +726,6 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
   }
 }
 
-// Block b of nb is dispatched to XCD b % 8; give each XCD a contiguous
-// range of logical tiles so neighbouring columns share that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  const int q = nb / 8, r = nb % 8, x = b % 8, pos = b / 8;
-  return x * q + min(x, r) + pos;
-}
-
 template <typename T, bool YEE>
 __device__ __forceinline__ void march_tile(const EmLaunch &L, const EmPtrs<T> &p, int64_t step, int tx, int ty, int kc,
                                            int kchunk, int acc_joule) {

@@ -250,6 +250,13 @@ hipError_t launch_cg_apply_alpha(const MechGrid &M, const CgVecs<T> &v, double *
 // coarsest level is solved with a dense inverse.
 constexpr int kMgMaxLevels = 16;
 constexpr int kMgDeg = 4;   // most Chebyshev steps before (and after) the coarse correction
+// Block b of nb is dispatched to XCD b % 8; give each XCD a contiguous
+// range of logical tiles so that neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb / 8, r = nb % 8, x = b % 8, pos = b / 8;
+  return x * q + (x < r ? x : r) + pos;
+}
+
 constexpr int kMgUpper = 14;  // stored stencil blocks: the centre and the 13 offsets after it
 // Entry (r, c) of stored stencil block q of node `node` on a level of n nodes:
 // the three entries of a block row are contiguous, so a wave reads a row of

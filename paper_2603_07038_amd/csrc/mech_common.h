@@ -175,8 +175,13 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
   __shared__ T xs[3][3][CY + 1][CX + 1];
   __shared__ T co[24][CY][CX];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * CX + tx;
-  const int i0 = blockIdx.x * (CX - 1), j0 = blockIdx.y * (CY - 1);
-  const int k0 = blockIdx.z * kchunk, k1 = min(k0 + kchunk, g.nz + 1);
+  // logical tile of this block: XCD-contiguous, x fastest, so tiles that
+  // share cache lines at their x and y borders share an L2
+  const int nbx = int(gridDim.x), nby = int(gridDim.y);
+  const int lb = xcd_remap((int(blockIdx.z) * nby + int(blockIdx.y)) * nbx + int(blockIdx.x), nbx * nby * int(gridDim.z));
+  const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+  const int i0 = bx * (CX - 1), j0 = by * (CY - 1);
+  const int k0 = bz * kchunk, k1 = min(k0 + kchunk, g.nz + 1);
   const int ci = i0 - 1 + tx, cj = j0 - 1 + ty;
   const bool cin = ci >= 0 && ci < g.nx && cj >= 0 && cj < g.ny;
   const int ni = i0 + tx, nj = j0 + ty;

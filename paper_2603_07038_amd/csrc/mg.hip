@@ -38,13 +38,18 @@ namespace {
 
 using namespace mech;
 
-// Node (i, j) of the thread in a plane of (nx + 1) x (ny + 1) nodes: the
-// plane's nodes are numbered x fastest and cut into blocks of BX * BY
-// threads, so the coarse levels' short rows (129, 65, 33 nodes) fill the
-// waves instead of leaving up to half of each 64-wide row tile idle.
-// Threads past the end of the plane get j > ny.
-__device__ __forceinline__ void plane_node(int nx, int &i, int &j) {
-  const int t = int(blockIdx.x) * (BX * BY) + int(threadIdx.y) * BX + int(threadIdx.x);
+// Node (i, j, k) of the thread in a level launched on lgrid: each plane's
+// (nx + 1) x (ny + 1) nodes are numbered x fastest and cut into blocks of
+// BX * BY threads, so the coarse levels' short rows (129, 65, 33 nodes) fill
+// the waves instead of leaving up to half of each 64-wide row tile idle;
+// the blocks are taken in XCD-contiguous order, so the blocks holding the
+// rows j - 1, j, j + 1 of a plane share an L2.  Threads past the end of the
+// plane get j > ny.
+__device__ __forceinline__ void plane_node(int nx, int &i, int &j, int &k) {
+  const int nbx = int(gridDim.x);
+  const int lb = xcd_remap(int(blockIdx.z) * nbx + int(blockIdx.x), nbx * int(gridDim.z));
+  const int t = (lb % nbx) * (BX * BY) + int(threadIdx.y) * BX + int(threadIdx.x);
+  k = lb / nbx;
   j = t / (nx + 1);
   i = t - j * (nx + 1);
 }
@@ -160,9 +165,8 @@ __device__ __forceinline__ void inv3_live(const double Bin[9], uint8_t dead, dou
 template <typename T>
 __global__ __launch_bounds__(256) void mg_diag0_kernel(MechGrid M, T *Dinv, int64_t dn, uint8_t *dead) {
   const DevGrid &g = M.g;
-  int i, j;
-  plane_node(g.nx, i, j);
-  const int k = blockIdx.z;
+  int i, j, k;
+  plane_node(g.nx, i, j, k);
   if (i > g.nx || j > g.ny) return;
   const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
   double B[9] = {};
@@ -198,9 +202,8 @@ __global__ __launch_bounds__(256) void mg_diag0_kernel(MechGrid M, T *Dinv, int6
 // Nodal blocks of a stencil level: centre block, dead mask, inverse.
 template <typename T>
 __global__ __launch_bounds__(256) void mg_diag_kernel(MgLevel<T> L) {
-  int i, j;
-  plane_node(L.nx, i, j);
-  const int k = blockIdx.z;
+  int i, j, k;
+  plane_node(L.nx, i, j, k);
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   double B[9];
@@ -396,9 +399,8 @@ __global__ __launch_bounds__(256) void mg_galerkin_kernel(MgLevel<T> F, int cnx,
 // Deterministic start vector of the power iteration (dead DOFs zero).
 template <typename T>
 __global__ __launch_bounds__(256) void mg_start_kernel(MgLevel<T> L, V3<T> v) {
-  int i, j;
-  plane_node(L.nx, i, j);
-  const int k = blockIdx.z;
+  int i, j, k;
+  plane_node(L.nx, i, j, k);
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   const uint8_t dd = L.dead[n];
@@ -429,9 +431,8 @@ __device__ __forceinline__ void power_sums(const double u[3], const double y[3],
 template <typename T>
 __global__ __launch_bounds__(256) void mg_power_kernel(MgLevel<T> L, V3<T> v, V3<T> w,
                                                        const double *scale, double *partials) {
-  int i, j;
-  plane_node(L.nx, i, j);
-  const int k = blockIdx.z;
+  int i, j, k;
+  plane_node(L.nx, i, j, k);
   double red[3] = {0.0, 0.0, 0.0};
   if (i <= L.nx && j <= L.ny) {
     const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
@@ -489,9 +490,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void mg_smooth_kernel(MgLevel<T> L, V3<T> b, V3<T> xin, V3<T> xout,
                                                         T c1, T c2, int first, const DevScalars *sc) {
   if (sc && sc->done) return;
-  int i, j;
-  plane_node(L.nx, i, j);
-  const int k = blockIdx.z;
+  int i, j, k;
+  plane_node(L.nx, i, j, k);
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   T r[3];
@@ -521,9 +521,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void mg_resid_kernel(MgLevel<T> L, V3<T> b, V3<T> x, V3<T> r,
                                                        const DevScalars *sc) {
   if (sc && sc->done) return;
-  int i, j;
-  plane_node(L.nx, i, j);
-  const int k = blockIdx.z;
+  int i, j, k;
+  plane_node(L.nx, i, j, k);
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   T y[3];
@@ -539,9 +538,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void mg_restrict_kernel(MgLevel<T> F, V3<T> r, MgLevel<T> C, int smooth, T c2,
                                                           const DevScalars *sc) {
   if (sc && sc->done) return;
-  int I, J;
-  plane_node(C.nx, I, J);
-  const int K = blockIdx.z;
+  int I, J, K;
+  plane_node(C.nx, I, J, K);
   if (I > C.nx || J > C.ny) return;
   const int fi0 = F.ax[0].cpos[I], fj0 = F.ax[1].cpos[J], fk0 = F.ax[2].cpos[K];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -576,9 +574,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void mg_prolong_kernel(MgLevel<T> F, V3<T> x, MgLevel<T> C, V3<T> xc,
                                                          const DevScalars *sc) {
   if (sc && sc->done) return;
-  int i, j;
-  plane_node(F.nx, i, j);
-  const int k = blockIdx.z;
+  int i, j, k;
+  plane_node(F.nx, i, j, k);
   if (i > F.nx || j > F.ny) return;
   const int64_t n = int64_t(k) * F.sz + int64_t(j) * F.sy + i;
   const int lx = F.ax[0].lo[i], ly = F.ax[1].lo[j], lz = F.ax[2].lo[k];
@@ -605,9 +602,8 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(MgLevel<T> F, V3<T> x, 
 template <typename T>
 __global__ __launch_bounds__(256) void mg_zero_kernel(MgLevel<T> L, V3<T> x, const DevScalars *sc) {
   if (sc && sc->done) return;
-  int i, j;
-  plane_node(L.nx, i, j);
-  const int k = blockIdx.z;
+  int i, j, k;
+  plane_node(L.nx, i, j, k);
   if (i > L.nx || j > L.ny) return;
   const int64_t n = int64_t(k) * L.sz + int64_t(j) * L.sy + i;
   x.c[0][n] = T(0); x.c[1][n] = T(0); x.c[2][n] = T(0);
@@ -766,9 +762,8 @@ __global__ __launch_bounds__(256) void cgmg_dot_kernel(MechGrid M, CgVecs<T> v, 
                                                        double *partials) {
   if (sc->done) return;
   const DevGrid &g = M.g;
-  int i, j;
-  plane_node(g.nx, i, j);
-  const int k = blockIdx.z;
+  int i, j, k;
+  plane_node(g.nx, i, j, k);
   double rz = 0.0;
   if (i <= g.nx && j <= g.ny) {
     const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
