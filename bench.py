@@ -249,16 +249,6 @@ def temporal_leg(steps=100, warmup=10, slabs=(0, 3, 8)):
     import workloads as W
     import paper_2603_07038_amd as etm
     prob = W.config2()
-    if kind == "mech":
-        dt = etm.cfl_dt(prob)
-        R = prob.em_per_thermal
-        J = prob.sample_J_half(dt, 2 * R + 2)
-        plan = etm.Plan(prob, J, dt=dt, precision=etm.ETM_PREC_MIXED, n_steps=2 * R + 2, history=False)
-        plan.advance(2 * R)
-        info = plan.sync()
-        print(json.dumps({"probe": kind, "workload": prob.name, "cells": prob.n_cells, "em_steps": 2 * R,
-                          "mech_solves": info["n_solves"], "cg_iters_total": info["cg_iters_total"]}))
-        return
     prob.mech_every_thermal = 0
     prob.em_per_thermal = 100000
     prob.history_stride = 0
