@@ -22,7 +22,7 @@ Beside the headline, the same JSON line carries:
              two-step slab wavefront over 8 z-slabs (temporal blocking);
   temporal_blocking  the slice's EM march per step with the two-step slab
              wavefront over 3 and 8 z-slabs against one launch per step;
-  excitation the same package under the excitation scheme of Sec. 3.3 (52,640
+  excitation the same package under the excitation scheme of Sec. III-B (52,640
              port edges, one closed-form wave per port sampled on the
              device): EM march rate, mixed;
   batch      64 design variants of uneven size (64x64x32 .. 192x192x48,
@@ -272,7 +272,7 @@ def temporal_leg(steps=100, warmup=10, slabs=(0, 3, 8)):
 
 def excitation_leg(steps=256, warmup=8, t_origin=95e-12):
     """EM march of the 1024x1024x128 package under the excitation scheme of
-    Sec. 3.3 (one closed-form wave per port, sampled on the device in blocks
+    Sec. III-B (one closed-form wave per port, sampled on the device in blocks
     of steps), mixed precision, in a window where the 5 GHz sine and the
     40 GHz burst are on; the march rate against the tabulated-PRBS package
     of the fullscale leg, and the host table the device sampling avoids for

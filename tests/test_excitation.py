@@ -1,4 +1,4 @@
-"""The excitation scheme of Sec. 3.3 (CPU): closed-form facts of each
+"""The excitation scheme of Sec. III-B (CPU): closed-form facts of each
 waveform, the jitter bounds, the port layout (differential pairs, balanced
 Ground-Signal-Ground groups) and the library's host-side validation of
 closed-form wave records."""

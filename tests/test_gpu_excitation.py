@@ -1,4 +1,4 @@
-"""The excitation scheme of Sec. 3.3 on the GPU: closed-form waves evaluated
+"""The excitation scheme of Sec. III-B on the GPU: closed-form waves evaluated
 on the device against the same waves sampled on the host (tabulated path)
 and against the oracle, which marches with the sampled values; both
 precisions and the batched path.  Time origins put the Ricker trigger and

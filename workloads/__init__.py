@@ -219,7 +219,7 @@ class Problem:
 
 
 # ---------------------------------------------------------------------------
-# The excitation scheme of Sec. 3.3.  Trace ports form differential pairs
+# The excitation scheme of Sec. III-B.  Trace ports form differential pairs
 # (alternating polarity along y) driven by a Ricker "trigger"; bump arrays
 # are fed as Ground-Signal-Ground groups of x-directed current ports, driven
 # by a 5 GHz sine under the logic die and by a 40 GHz carrier under a 3-bit
@@ -432,7 +432,7 @@ def config2(seed: int = 2001, excitation: str = "prbs", t_origin: float = 0.0) -
     through 50 ohm.  PMC on all faces; kinematic mount.  20,000 EM steps,
     R = 200 (100 thermal steps), a PCG solve after every thermal step.
 
-    excitation="paper": the scheme of Sec. 3.3 instead (closed-form waves,
+    excitation="paper": the scheme of Sec. III-B instead (closed-form waves,
     one per port, times measured from t_origin): the trace ports become
     differential pairs driven by the Ricker trigger (+-1 V alternating along
     y) and the bumps Ground-Signal-Ground groups under the two dies.
@@ -518,7 +518,7 @@ def package(nx: int, ny: int, nz: int, seed: int, *, bump_pitch_um: float = 16.0
     one-cell gap near its start by its own seeded PRBS-7 burst (1 V through
     50 ohm, rise = a quarter bit).
 
-    excitation="paper": the scheme of Sec. 3.3 instead (closed-form waves,
+    excitation="paper": the scheme of Sec. III-B instead (closed-form waves,
     one per port, times measured from t_origin): the traces become
     differential pairs driven by the Ricker trigger (+-1 V alternating in
     trace order) and every bump column a Ground-Signal-Ground line, under
@@ -619,7 +619,7 @@ def config3(seed: int = 3001, excitation: str = "prbs", t_origin: float = 0.0) -
     bumps of 8x8 cells at 16-cell pitch, 8 RDL routing layers x 512 traces
     (width 1, pitch 2, alternating x/y) = 4096 traces, each with a 256-bit
     PRBS-7 burst at 16 steps per bit (4096 EM steps), R = 256.
-    excitation="paper": the Sec. 3.3 scheme on the same geometry."""
+    excitation="paper": the Sec. III-B scheme on the same geometry."""
     return package(1024, 1024, 128, seed, bump_pitch_um=16, bump_cells=8, trace_width=1,
                    trace_pitch=2, n_trace_layers=8, n_bits=256, steps_per_bit=16,
                    em_per_thermal=256, name="package1024x1024x128" + ("_paperexc" if excitation == "paper" else ""),
