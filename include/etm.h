@@ -282,6 +282,26 @@ etm_status etm_batch_create(int32_t max_slots, const char *tune_json, etm_batch 
 etm_status etm_batch_attach(etm_batch *batch, etm_plan *plan, int32_t *slot);
 etm_status etm_batch_detach(etm_batch *batch, int32_t slot);
 etm_status etm_batch_advance(etm_batch *batch, int64_t n_em_steps, void *hip_stream);
+
+/* etm_batch_advance for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, hosts that forbid
+ * hipMalloc): the same steps with the same kernels and bitwise the same
+ * results, but the variant descriptors, the work list and the step counter
+ * live in a fixed 4 MiB array of device memory that the library holds on
+ * each GPU until the process ends, the work list is generated on the device,
+ * and every step is launched directly (no graphs).  The call makes no
+ * hipMalloc / hipFree / graph instantiation; the batch and its plans must
+ * already exist and be bound.
+ * Limits (ETM_E_INVAL beyond them, nothing enqueued): at most 64 attached
+ * variants; at most 259,344 march tiles over all variants (a tile is 62 x 4
+ * nodes by one z-chunk in mixed precision, 64 x 4 in FP64); attached plans
+ * must not schedule mechanical solves (mech_every_thermal = 0); every plan's
+ * workspace must be on the device that was current at etm_batch_create.
+ * The array is shared by every call on one GPU and keeps the last call's
+ * contents: calls that overlap on one GPU (two batches advanced from
+ * different host threads or on unordered streams) race and must be
+ * serialised by the caller.  Errors as etm_batch_advance. */
+etm_status etm_batch_advance_noalloc(etm_batch *batch, int64_t n_em_steps, void *hip_stream);
 void etm_batch_destroy(etm_batch *batch);
 
 const char *etm_last_error(void);

@@ -126,6 +126,7 @@ def load():
         "etm_batch_attach": [_P, _P, C.POINTER(C.c_int32)],
         "etm_batch_detach": [_P, C.c_int32],
         "etm_batch_advance": [_P, C.c_int64, _P],
+        "etm_batch_advance_noalloc": [_P, C.c_int64, _P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -388,6 +389,13 @@ class Batch:
         import torch
         st = stream if stream is not None else torch.cuda.current_stream()
         check(load().etm_batch_advance(self.h, int(n), C.c_void_p(st.cuda_stream)))
+
+    def advance_noalloc(self, n, stream=None):
+        """etm_batch_advance_noalloc: the same steps from the library's fixed
+        device scratch, without any device allocation or graph."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        check(load().etm_batch_advance_noalloc(self.h, int(n), C.c_void_p(st.cuda_stream)))
 
     def __del__(self):
         try:

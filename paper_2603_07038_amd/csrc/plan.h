@@ -1,4 +1,4 @@
-// Private host-side plan of the library (shared by plan.cpp and batch.cpp).
+// Private host-side plan of the library (shared by plan.cpp and batch.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 
