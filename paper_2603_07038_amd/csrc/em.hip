@@ -388,12 +388,44 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
   const int pec = g.pec;
   const bool pec_i = (i == 0 && (pec & 1)) || (i == nx && (pec & 2));
   const bool pec_j = (j == 0 && (pec & 4)) || (j == ny && (pec & 8));
+  // Plane k + 2 is fetched into registers while plane k is computed and
+  // written to LDS at the top of the next iteration, so a block's global
+  // loads overlap its own arithmetic instead of stalling at the barrier.
+  constexpr int NPF = (TYH * TXH + BX * BY - 1) / (BX * BY);
+  T pf[NPF][3];
+  auto fetch = [&](int kk) {
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int t = tid + q * BX * BY;
+      const int r = t / TXH, c = t - r * TXH;
+      const int gi = i0 - 1 + c, gj = j0 - 1 + r;
+      const bool ok = t < TYH * TXH && kk >= 0 && kk <= nz && gi >= 0 && gi <= nx && gj >= 0 && gj <= ny;
+      const uint32_t qq = ok ? uint32_t(kk) * sz + uint32_t(gj) * sy + uint32_t(gi) : 0u;
+      pf[q][0] = ok ? p.e[qq] : T(0);
+      pf[q][1] = ok ? p.e[cs + qq] : T(0);
+      pf[q][2] = ok ? p.e[2 * cs + qq] : T(0);
+    }
+  };
+  auto commit = [&](int slot) {
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int t = tid + q * BX * BY;
+      if (t < TYH * TXH) {
+        const int r = t / TXH, c = t - r * TXH;
+        S.e[slot][0][r][c] = pf[q][0];
+        S.e[slot][1][r][c] = pf[q][1];
+        S.e[slot][2][r][c] = pf[q][2];
+      }
+    }
+  };
   int s_m = 0, s_0 = 1, s_p = 2;
   load_plane(k0 - 1, s_m);
   load_plane(k0, s_0);
+  fetch(k0 + 1);
   for (int k = k0; k < k1; ++k) {
-    load_plane(k + 1, s_p);
+    commit(s_p);
     __syncthreads();
+    if (k + 2 <= k1) fetch(k + 2);
     if (active) {
       const uint32_t n = uint32_t(k) * sz + uint32_t(j) * sy + uint32_t(i);
       const bool pec_k = (k == 0 && (pec & 16)) || (k == nz && (pec & 32));
@@ -953,6 +985,9 @@ __global__ __launch_bounds__(256) void thermal_kernel(ThermalLaunch L, const T *
       if (P != 0.0) ps += P;
     }
     thermal_node(L, i, j, k, n, ps, e_part, m_part);
+    // the max reduction (fmax) drops NaN: carry a non-finite temperature in
+    // the energy sum, which the finalize kernel checks
+    if (!isfinite(m_part)) e_part = m_part - m_part;
   }
   const double s[1] = {e_part}, m[1] = {m_part};
   const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;

@@ -229,6 +229,8 @@ hipError_t launch_residual64(const MechGrid &M, const double *f[3], const double
                              double *partials, DevScalars *sc, hipStream_t s);
 hipError_t launch_vec_cast(const void *src, int src_f32, void *dst, int dst_f32, int64_t n, hipStream_t s);
 hipError_t launch_vec_axpy64(double *y, const float *x, int64_t n, hipStream_t s);  // y += x
+// u_c <- 0 at every fixed DOF c of the plan's constraints
+hipError_t launch_mask_fixed(const MechGrid &M, int c, double *u, hipStream_t s);
 // u <- u + sc (u - uprev), uprev <- previous u
 hipError_t launch_extrapolate(double *u[3], double *uprev[3], double sc, int64_t n, hipStream_t s);
 hipError_t launch_von_mises(const MechGrid &M, const double *theta, const double *u[3], double *vm,

@@ -241,6 +241,12 @@ __global__ void cast_kernel(const void *src, int src_f32, void *dst, int dst_f32
   }
 }
 
+// u_c <- 0 at every node whose DOF c is fixed.
+__global__ void mask_fixed_kernel(const uint8_t *fixed, int c, double *u, int64_t n) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+    if (fixed[t] >> c & 1) u[t] = 0.0;
+}
+
 // u <- u + s (u - u_prev), u_prev <- old u (per component arrays).
 __global__ void extrapolate_kernel(double *u0, double *u1, double *u2, double *v0, double *v1, double *v2, double sc,
                                    int64_t n) {
@@ -377,6 +383,11 @@ hipError_t launch_vec_cast(const void *src, int src_f32, void *dst, int dst_f32,
 hipError_t launch_extrapolate(double *u[3], double *uprev[3], double sc, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(extrapolate_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, u[0], u[1], u[2], uprev[0], uprev[1],
                      uprev[2], sc, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_fixed(const MechGrid &M, int c, double *u, hipStream_t s) {
+  hipLaunchKernelGGL(mask_fixed_kernel, dim3(flat_blocks(M.g.ntot)), dim3(256), 0, s, M.fixed, c, u, M.g.ntot);
   return hipGetLastError();
 }
 

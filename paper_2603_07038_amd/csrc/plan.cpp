@@ -1354,9 +1354,12 @@ etm_status etm_write(etm_plan *p, int32_t field, const void *src, size_t bytes, 
     if (st != ETM_OK) return st;
   }
   if (field >= ETM_FIELD_UX && field <= ETM_FIELD_UZ) {
-    // keep fixed DOFs at zero
-    std::vector<double> h(need / 8);
-    HIP_TRY(hipStreamSynchronize(p->stream));
+    // a fixed DOF carries no displacement: clear what was written there
+    // (the solves would otherwise take it as a prescribed displacement)
+    HIP_TRY(launch_mask_fixed(p->mech_grid(), field - ETM_FIELD_UX, static_cast<double *>(dstp), p->stream));
+    // the next solve's starting point comes from this displacement
+    HIP_TRY(hipMemcpyAsync(p->ptr<double>(p->r_uprev64[field - ETM_FIELD_UX]), dstp, size_t(p->ntot) * 8,
+                           hipMemcpyDeviceToDevice, p->stream));
   }
   HIP_TRY(hipStreamSynchronize(p->stream));
   return ETM_OK;

@@ -29,7 +29,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from . import ETM_FIELD_THETA, ETM_FIELD_VM, ETM_PREC_MIXED, Batch, Plan, cfl_dt
+from . import ETM_FIELD_THETA, ETM_FIELD_VM, ETM_PREC_MIXED, Batch, EtmError, Plan, cfl_dt
 
 
 @dataclasses.dataclass
@@ -37,6 +37,7 @@ class Request:
     prob: object          # workloads.Problem
     arrival: float = 0.0  # seconds after the server starts
     rid: int = 0
+    opts: Optional[dict] = None  # plan option overrides (e.g. {"cg_maxit": 500})
 
 
 @dataclasses.dataclass
@@ -54,6 +55,8 @@ class Result:
     cg_relres: float
     theta: Optional[np.ndarray] = None
     vm: Optional[np.ndarray] = None
+    status: str = "ok"    # "ok"; "rejected" (footprint above the HBM budget); "error" (see message)
+    message: str = ""
 
     @property
     def latency(self):
@@ -84,12 +87,16 @@ class Server:
         p = req.prob
         dt = cfl_dt(p)
         J = p.sample_J_half(dt, p.n_em_steps)
-        plan = Plan(p, J, dt=dt, precision=self.precision, n_steps=p.n_em_steps, history=False, bind=False)
+        plan = Plan(p, J, dt=dt, precision=self.precision, n_steps=p.n_em_steps, history=False, bind=False,
+                    **(req.opts or {}))
         return plan
 
+    def _reject(self, req: Request, plan, now: float, status: str, message: str) -> Result:
+        return Result(rid=req.rid, name=req.prob.name, cells=req.prob.n_cells, em_steps=req.prob.n_em_steps,
+                      arrival=req.arrival, admitted=now, finished=now, theta_max=float("nan"), vm_max=float("nan"),
+                      cg_iters=0, cg_relres=float("nan"), status=status, message=message)
+
     def _admit(self, req: Request, plan, now: float) -> bool:
-        if plan.footprint > self.hbm_budget:
-            raise ValueError(f"request {req.rid} needs {plan.footprint} B, above the HBM budget")
         if len(self.active) >= self.max_slots or self.used + plan.footprint > self.hbm_budget:
             return False
         torch = self.torch
@@ -104,12 +111,17 @@ class Server:
         return True
 
     def _finish(self, plan):
-        """Worker thread: solve, von Mises, read back; returns (info, theta, vm, time)."""
-        plan.mech_solve()
-        info = plan.sync()
+        """Worker thread: solve, von Mises, read back; returns (info, theta, vm,
+        time, error message or "")."""
+        err = ""
+        try:
+            plan.mech_solve()
+        except EtmError as e:   # e.g. ETM_E_NOCONV: this request fails, the others go on
+            err = str(e)
+        info = plan.sync(raise_on_error=False)
         theta = plan.read(ETM_FIELD_THETA)
         vm = plan.read(ETM_FIELD_VM)
-        return info, theta, vm, time.perf_counter() - self._t0
+        return info, theta, vm, time.perf_counter() - self._t0, err
 
     def _retire(self, slot: int):
         req, plan, admitted, _ = self.active.pop(slot)
@@ -127,14 +139,24 @@ class Server:
             if not fut.done():
                 keep.append([fut, req, plan, admitted])
                 continue
-            info, theta, vm, finished = fut.result()
-            done.append(Result(rid=req.rid, name=req.prob.name, cells=req.prob.n_cells, em_steps=req.prob.n_em_steps,
-                               arrival=req.arrival, admitted=admitted, finished=finished,
-                               theta_max=float(theta.max()), vm_max=float(vm.max()), cg_iters=int(info["cg_iters"]),
-                               cg_relres=float(info["cg_relres"]), theta=theta if self.keep_fields else None,
-                               vm=vm if self.keep_fields else None))
-            self.used -= plan.footprint
-            plan.ws = None
+            try:
+                info, theta, vm, finished, err = fut.result()
+                if not err and info["status"] != 0:
+                    err = f"asynchronous status {info['status']}"
+                done.append(Result(rid=req.rid, name=req.prob.name, cells=req.prob.n_cells,
+                                   em_steps=req.prob.n_em_steps, arrival=req.arrival, admitted=admitted,
+                                   finished=finished, theta_max=float(theta.max()), vm_max=float(vm.max()),
+                                   cg_iters=int(info["cg_iters"]), cg_relres=float(info["cg_relres"]),
+                                   theta=theta if self.keep_fields else None, vm=vm if self.keep_fields else None,
+                                   status="error" if err else "ok", message=err))
+            except Exception as e:  # a failure of one request never stops the loop
+                now = time.perf_counter() - self._t0
+                r = self._reject(req, plan, now, "error", repr(e))
+                r.admitted = admitted
+                done.append(r)
+            finally:
+                self.used -= plan.footprint
+                plan.ws = None
         self.solving = keep
 
     def run(self, requests: List[Request], realtime: bool = True) -> List[Result]:
@@ -149,7 +171,18 @@ class Server:
             t = now()
             while pending and (not realtime or pending[0].arrival <= t):
                 r = pending.pop(0)
-                queue.append((r, self._make_plan(r)))
+                try:
+                    plan = self._make_plan(r)
+                except EtmError as e:   # invalid request: answered at once
+                    done.append(self._reject(r, None, now(), "error", str(e)))
+                    continue
+                if plan.footprint > self.hbm_budget:
+                    # can never fit: answered at once instead of blocking the queue
+                    done.append(self._reject(r, plan, now(), "rejected",
+                                             f"needs {plan.footprint} B of device memory, above the "
+                                             f"{int(self.hbm_budget)} B budget"))
+                    continue
+                queue.append((r, plan))
             self._collect(done)
             while queue:
                 r, plan = queue[0]
@@ -175,7 +208,13 @@ class Server:
 
 
 def summarize(results: List[Result], wall: float) -> dict:
-    lat = np.array([r.latency for r in results]) if results else np.zeros(1)
-    return {"requests": len(results), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean()), "designs_per_hour": len(results) / wall * 3600.0 if wall > 0 else None,
-            "cell_steps": int(sum(r.cells * r.em_steps for r in results)), "wall_s": wall}
+    """Latency percentiles and throughput over the requests that finished;
+    rejected and failed requests are counted beside them."""
+    ok = [r for r in results if r.status == "ok"]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    return {"requests": len(results), "completed": len(ok),
+            "rejected": sum(r.status == "rejected" for r in results),
+            "failed": sum(r.status == "error" for r in results),
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "designs_per_hour": len(ok) / wall * 3600.0 if wall > 0 else None,
+            "cell_steps": int(sum(r.cells * r.em_steps for r in ok)), "wall_s": wall}

@@ -1,0 +1,108 @@
+"""Failure handling, forced from the host so that every kernel still exits
+normally: a mechanical solve stopped at cg_maxit = 1 reports ETM_E_NOCONV,
+a non-finite temperature or field trips the device watchdog (ETM_E_UNSTABLE
+at etm_sync), the server answers an over-budget request with a rejection
+and a non-converging one with an error while the other requests finish,
+and a displacement written through etm_write keeps the constraints (its
+fixed DOFs read back as zero and the next solve matches the oracle)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2603_07038_amd as etm
+import workloads as W
+from paper_2603_07038_amd import serve
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(prob, n, **kw):
+    dt = etm.cfl_dt(prob)
+    return etm.Plan(prob, prob.sample_J_half(dt, n + 1), dt=dt, n_steps=n, history=False, **kw)
+
+
+@pytest.mark.parametrize("prec", [etm.ETM_PREC_FP64, etm.ETM_PREC_MIXED])
+def test_cg_maxit_one_reports_noconv(prec):
+    prob = W.random_problem(21, 9, 7, 5, n_steps=8, R=4, mech_bc=W.MECH_CLAMP_ZMIN)
+    plan = _plan(prob, 8, precision=prec, cg_maxit=1)
+    th = np.random.default_rng(21).uniform(0, 30, (prob.nz + 1, prob.ny + 1, prob.nx + 1))
+    plan.write(etm.ETM_FIELD_THETA, th)
+    with pytest.raises(etm.EtmError) as ei:
+        plan.mech_solve()
+    assert ei.value.status == etm.ETM_E_NOCONV
+    info = plan.sync(raise_on_error=False)
+    assert info["status"] == etm.ETM_E_NOCONV and info["cg_iters"] <= 1 and info["cg_relres"] > prob.cg_rtol
+    with pytest.raises(etm.EtmError) as ei:
+        plan.sync()
+    assert ei.value.status == etm.ETM_E_NOCONV
+
+
+@pytest.mark.parametrize("field", [etm.ETM_FIELD_THETA, etm.ETM_FIELD_EX])
+def test_nonfinite_value_trips_the_watchdog(field):
+    prob = W.random_problem(22, 12, 9, 6, n_steps=16, R=4, n_ports=2, amp=3e10)
+    plan = _plan(prob, 16)
+    plan.advance(4)
+    assert plan.sync()["status"] == etm.ETM_OK
+    x = plan.read(field)
+    x[2, 3, 4] = np.nan
+    plan.write(field, x)
+    plan.advance(4)                       # a thermal step sees it
+    info = plan.sync(raise_on_error=False)
+    assert info["status"] == etm.ETM_E_UNSTABLE
+    with pytest.raises(etm.EtmError) as ei:
+        plan.sync()
+    assert ei.value.status == etm.ETM_E_UNSTABLE
+
+
+@pytest.mark.parametrize("bc", [W.MECH_KINEMATIC, W.MECH_CLAMP_ZMIN])
+def test_written_displacement_keeps_constraints(bc):
+    prob = W.random_problem(23, 8, 7, 4, n_steps=4, R=2, mech_bc=bc, void_top=1)
+    prob.cg_rtol = 1e-12
+    o = oracle.Oracle(prob)
+    plan = _plan(prob, 4)
+    rng = np.random.default_rng(23)
+    th = rng.uniform(0, 30, o.node_shape)
+    plan.write(etm.ETM_FIELD_THETA, th)
+    mask = o.mech_mask()
+    # a random displacement, nonzero at the fixed DOFs too
+    u0 = rng.uniform(-1e-7, 1e-7, o.node_shape + (3,))
+    for c, f in enumerate((etm.ETM_FIELD_UX, etm.ETM_FIELD_UY, etm.ETM_FIELD_UZ)):
+        plan.write(f, u0[..., c])
+        back = plan.read(f)
+        fixed = (mask >> c & 1).astype(bool)
+        assert fixed.any()
+        np.testing.assert_array_equal(back[fixed], 0.0)
+        np.testing.assert_array_equal(back[~fixed], u0[..., c][~fixed])
+    plan.mech_solve()
+    info = plan.sync()
+    assert info["cg_relres"] <= prob.cg_rtol
+    q, _, _ = o.mech_solve(th, mask, rtol=1e-13)
+    scale = np.abs(q).max()
+    assert np.abs(plan.u() - q).max() <= 1e-8 * scale
+    vm_o = o.von_mises(th, q)
+    assert np.abs(plan.read(etm.ETM_FIELD_VM) - vm_o).max() <= 1e-8 * vm_o.max()
+
+
+def _req(r, n, bits, **opts):
+    p = W.package(n, n - 2, 24, 7300 + r, bump_pitch_um=20, bump_cells=8, trace_width=2, trace_pitch=4,
+                  n_trace_layers=2, max_traces=6, n_bits=bits, steps_per_bit=4, em_per_thermal=64,
+                  name=f"freq{r}")
+    return serve.Request(prob=p, arrival=0.01 * r, rid=r, opts=opts or None)
+
+
+def test_server_rejects_over_budget_and_isolates_failures():
+    small = [_req(0, 24, 32), _req(1, 26, 48, cg_maxit=1), _req(2, 22, 32)]
+    big = _req(3, 64, 32)
+    fp = [_plan(q.prob, q.prob.n_em_steps, bind=False, precision=etm.ETM_PREC_MIXED).footprint for q in small + [big]]
+    budget = 2.5 * max(fp[:3])
+    assert fp[3] > budget
+    srv = serve.Server(max_slots=2, hbm_budget=budget, precision=etm.ETM_PREC_MIXED, chunk=32)
+    done = {r.rid: r for r in srv.run(small + [big], realtime=True)}
+    assert sorted(done) == [0, 1, 2, 3]
+    assert done[3].status == "rejected" and "budget" in done[3].message
+    assert done[1].status == "error" and "ETM_E_NOCONV" in done[1].message
+    for rid in (0, 2):
+        assert done[rid].status == "ok" and done[rid].cg_relres <= 1e-8 and done[rid].em_steps == 128
+    assert srv.used == 0.0 and not srv.active and not srv.solving
+    summ = serve.summarize(list(done.values()), 1.0)
+    assert summ["completed"] == 2 and summ["rejected"] == 1 and summ["failed"] == 1
