@@ -10,8 +10,9 @@
  *   2. the Joule source P = D_sigma e^2 (Sec. II-A, below Eq. 4);
  *   3. transient conduction by forward Euler, Eq. (4)-(5), every R EM steps
  *      with the block-mean Joule source (R = 1 is the paper's schedule);
- *   4. the thermoelastic HEX8 system, Eq. (7)-(8), by Jacobi-preconditioned
- *      CG, and the centroid von Mises stress, Eq. (9);
+ *   4. the thermoelastic HEX8 system, Eq. (7)-(8), by CG preconditioned with
+ *      a geometric multigrid V-cycle (or nodal Jacobi), and the centroid von
+ *      Mises stress, Eq. (9);
  * on one GPU.  Device memory is owned by the caller (e.g. a torch tensor)
  * and handed to the plan as one workspace; all GPU work is enqueued on the
  * caller's HIP stream.
@@ -56,7 +57,7 @@ enum { ETM_MECH_KINEMATIC = 0, ETM_MECH_CLAMP_ZMIN = 1 };   /* mechanical suppor
 enum { ETM_PREC_FP64 = 0, ETM_PREC_MIXED = 1 };
 /* Preconditioner of the mechanical CG (Eq. 8): nodal Jacobi, or a geometric
  * multigrid V-cycle with Galerkin coarse operators (the role the paper's
- * algebraic multigrid plays, Sec. 4.1). */
+ * algebraic multigrid plays, Sec. IV-A). */
 enum { ETM_PRECOND_JACOBI = 0, ETM_PRECOND_MG = 1 };
 
 /* Fields for etm_read / etm_write (always FP64, natural shapes). */
@@ -101,7 +102,7 @@ typedef struct {
 } etm_port;
 
 /* Closed-form excitation waveforms, evaluated on the device at every EM step
- * (the transient excitation scheme of Sec. 3.3: a Ricker trigger, a sine
+ * (the transient excitation scheme of Sec. III-B: a Ricker trigger, a sine
  * "logic noise" and a Gaussian-pulse-train "data burst" on a carrier, each
  * with its own per-port amplitude, width and phase).  A wave is zero outside
  * [t_on, t_off); inside, with u = (t - t0) / width:
@@ -232,17 +233,31 @@ etm_status etm_plan_dofs(const etm_plan *plan, int64_t *em, int64_t *thermal, in
 etm_status etm_plan_bind(etm_plan *plan, void *device_ws, size_t bytes, void *hip_stream);
 
 /* Enqueue n_em_steps coupled steps (EM + Joule + thermal every R steps +
- * histories; scheduled mechanical solves run at their thermal steps and
- * wait on the host for convergence).  Asynchronous errors are reported by
- * etm_sync. */
+ * histories; a scheduled mechanical solve is enqueued at its thermal step,
+ * on the plan's side stream beside the following EM steps when mech_overlap
+ * is set).  Returns without waiting for the GPU, except that a scheduled
+ * solve first waits for the previous solve of the plan to be decided (it
+ * owns the displacement the next one starts from), and the first solve of a
+ * plan waits while it builds the multigrid hierarchy.  Asynchronous errors
+ * are reported by etm_sync. */
 etm_status etm_advance(etm_plan *plan, int64_t n_em_steps);
 
-/* Solve Eq. (8) for the current temperature (warm-started from the last
- * displacement) and evaluate Eq. (9).  Polls the device for convergence. */
+/* Enqueue a solve of Eq. (8) for the current temperature (warm-started from
+ * the last displacement) and the von Mises stress of Eq. (9) on the plan's
+ * stream, and return (same waits as above).  The solve's outer loop -- the
+ * FP64 residual check, the mixed path's FP32 corrections, the tolerance
+ * ||f - K u|| <= cg_rtol ||f|| and the cg_maxit limit -- is decided on the
+ * device; the host enqueues passes sized from the previous solve and, if
+ * the device has not decided the solve when they end, more passes at the
+ * next call that needs the result.  Its outcome (iterations, residual,
+ * ETM_E_NOCONV) is reported by etm_sync. */
 etm_status etm_mech_solve(etm_plan *plan);
 
-/* Wait for the plan's stream; fill info (may be NULL); return the first
- * asynchronous error (ETM_E_UNSTABLE on a non-finite field, ETM_E_NOCONV). */
+/* Wait for the plan's work (its stream and an enqueued solve); fill info (may
+ * be NULL); return the first asynchronous error (ETM_E_UNSTABLE on a
+ * non-finite field or temperature, ETM_E_NOCONV when a solve stopped at
+ * cg_maxit or made no progress).  etm_read, etm_write, etm_checkpoint and
+ * etm_restore also wait for an enqueued solve before they touch the state. */
 etm_status etm_sync(etm_plan *plan, etm_run_info *info);
 
 /* Copy a field out as FP64 in its natural shape (bytes must equal the

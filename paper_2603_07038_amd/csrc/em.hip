@@ -216,7 +216,7 @@ __device__ __forceinline__ int find_port(const DevPorts &P, int64_t key) {
   return -1;
 }
 
-// Value at time t of a closed-form wave (the excitation scheme of Sec. 3.3):
+// Value at time t of a closed-form wave (the excitation scheme of Sec. III-B):
 // a Ricker wavelet, a sine, or a Gaussian pulse train on a carrier, zero
 // outside [t_on, t_off).  Record: kind, n_pulses, amp, t0, width, freq,
 // t_on, t_off, pulse centres.

@@ -79,7 +79,14 @@ struct DevPorts {
   double *er;         // eps_r of each port edge (written by the coefficient kernel)
 };
 
-// Scalars kept on the device for a plan.
+// Scalars kept on the device.  A plan holds three sets: the march's (Joule
+// energy, max temperature, watchdog status, records), the inner CG's (rz,
+// alpha, beta, done, iters, tol2, budget) and the mechanical solve's control
+// block (fnorm2, tol2 = the FP64 target, rr = the true residual, done = the
+// solve's state, iters = inner iterations of all passes, outer = FP64
+// residual evaluations, pass_iters).  Every kernel of a solve that is gated
+// by a set returns at once while its `done` is nonzero.
+constexpr int kMaxPasses = 16;
 struct DevScalars {
   double ejoule;      // dissipated energy of completed thermal blocks [J]
   double theta_max;
@@ -90,7 +97,15 @@ struct DevScalars {
   double rz, pw, alpha, beta, rr, tol2;
   int32_t done, iters;
   double fnorm2;
+  // solve control: outer passes, iteration limit, inner budget
+  int32_t outer, maxit, budget, mixed;
+  double inner_rtol2;
+  int32_t pass_iters[kMaxPasses];
+  int32_t restart;    // inner CG: a new inner solve is due (set by the FP64 check, taken by the setup)
+  int32_t pad2;
 };
+// States of a solve's control block (its `done`).
+enum { kSolveRunning = 0, kSolveConverged = 1, kSolveGaveUp = 3 };
 
 // Reduction partials: per block, up to 4 doubles.
 constexpr int kRedWidth = 4;
@@ -212,7 +227,29 @@ struct MechGrid {
 hipError_t launch_mech_diag(const MechGrid &M, double *dinv[3], hipStream_t s);
 hipError_t launch_mech_rhs(const MechGrid &M, const double *theta, double *f[3], double *partials,
                            DevScalars *sc, double rtol, hipStream_t s);
-// CG building blocks (T = double or float vectors; scalars in double).
+// Start of a solve, after launch_mech_rhs wrote ctl->fnorm2 and ctl->tol2:
+// reset the control block (maxit, inner relative tolerance of the mixed
+// path's corrections) and the inner scalars; a zero load gives u = 0 and a
+// converged solve at once.
+hipError_t launch_solve_init(DevScalars *ctl, DevScalars *scm, int maxit, double inner_rtol2, int mixed,
+                             double *u[3], int64_t n, hipStream_t s);
+// The solve's FP64 check: r64 = f - K u64 and |r|^2 (skipped once the solve
+// is done), then on the device: book the inner iterations of the pass that
+// just ended, stop when |r| <= rtol |f| (converged) or when the iteration
+// limit is reached or a pass made no progress (gave up), else set the next
+// pass's inner tolerance and budget.
+hipError_t launch_residual_check(const MechGrid &M, const double *f[3], const double *u[3], double *r[3],
+                                 double *partials, DevScalars *ctl, DevScalars *scm, const DevScalars *gate,
+                                 hipStream_t s);
+// Gate words of a solve's two phases (their `done` = skip): gR for the
+// restart of the inner CG (skip unless the solve runs and a restart is due),
+// gF for the FP64 check and the refinement update (skip unless the solve
+// runs and the inner CG has finished).
+hipError_t launch_solve_gates(const DevScalars *ctl, const DevScalars *scm, DevScalars *gR, DevScalars *gF,
+                              hipStream_t s);
+// CG building blocks (T = double or float vectors; scalars in double).  The
+// setups take the solve's control block as a gate: once the solve is done
+// they mark the inner CG done, so a whole enqueued pass becomes a no-op.
 template <typename T>
 struct CgVecs {
   T *u[3], *r[3], *p[3], *w[3];
@@ -220,15 +257,18 @@ struct CgVecs {
 };
 template <typename T>
 hipError_t launch_cg_setup(const MechGrid &M, const CgVecs<T> &v, const T *rhs[3], double *partials,
-                           DevScalars *sc, hipStream_t s);
+                           DevScalars *sc, const DevScalars *gate, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_iteration(const MechGrid &M, const CgVecs<T> &v, double *partials, DevScalars *sc,
                                hipStream_t s);
 // FP64 true residual r64 = f - K u64, its norm into sc (rr), for refinement.
 hipError_t launch_residual64(const MechGrid &M, const double *f[3], const double *u[3], double *r[3],
                              double *partials, DevScalars *sc, hipStream_t s);
-hipError_t launch_vec_cast(const void *src, int src_f32, void *dst, int dst_f32, int64_t n, hipStream_t s);
-hipError_t launch_vec_axpy64(double *y, const float *x, int64_t n, hipStream_t s);  // y += x
+// Vector helpers of the refinement; gate (may be null) as above.
+hipError_t launch_vec_cast(const void *src, int src_f32, void *dst, int dst_f32, int64_t n, const DevScalars *gate,
+                           hipStream_t s);
+hipError_t launch_vec_zero32(float *x, int64_t n, const DevScalars *gate, hipStream_t s);
+hipError_t launch_vec_axpy64(double *y, const float *x, int64_t n, const DevScalars *gate, hipStream_t s);  // y += x
 // u_c <- 0 at every fixed DOF c of the plan's constraints
 hipError_t launch_mask_fixed(const MechGrid &M, int c, double *u, hipStream_t s);
 // u <- u + sc (u - uprev), uprev <- previous u
@@ -316,7 +356,7 @@ hipError_t launch_mg_vcycle(const MgDev<T> &G, V3<T> b, const DevScalars *sc, V3
 // Preconditioned CG with the V-cycle (vectors as for Jacobi CG; z in level-0 buffers).
 template <typename T>
 hipError_t launch_cgmg_setup(const MgDev<T> &G, const CgVecs<T> &v, const T *rhs[3], double *partials,
-                             DevScalars *sc, hipStream_t s);
+                             DevScalars *sc, DevScalars *gate, hipStream_t s);
 template <typename T>
 hipError_t launch_cgmg_iteration(const MgDev<T> &G, const CgVecs<T> &v, double *partials, DevScalars *sc,
                                  hipStream_t s);

@@ -1,7 +1,9 @@
 // gfx950 kernels of the thermoelastic solve (arXiv 2603.07038, Sec. II-B):
 // the HEX8 stiffness of Eq. (8) applied matrix-free, its thermal load, the
-// Jacobi-preconditioned CG that replaces the paper's closed AMG solver, and
-// the centroid von Mises stress of Eq. (9).
+// CG building blocks (nodal Jacobi preconditioning here, the multigrid
+// V-cycle in mg.hip; together they replace the paper's closed AMG solver),
+// the device-side outer loop of a solve (FP64 residual checks, refinement
+// updates, stop decisions), and the centroid von Mises stress of Eq. (9).
 //
 // Box elements.  Every cell is an axis-aligned box, so with trilinear shape
 // functions N_a = phi_ax(x) phi_ay(y) phi_az(z) each entry of the element
@@ -132,7 +134,9 @@ struct EpiJacobiStart {
   }
 };
 
-__global__ __launch_bounds__(256) void cg_setup_finalize(const double *part, int64_t nb, DevScalars *sc) {
+__global__ __launch_bounds__(256) void cg_setup_finalize(const double *part, int64_t nb, DevScalars *sc,
+                                                         const DevScalars *gate) {
+  if (gate && gate->done) return;  // no restart due: the inner CG goes on (or the solve is over)
   __shared__ double out[2];
   sum_partials<2>(part, nb, out);
   if (threadIdx.x == 0) {
@@ -141,6 +145,7 @@ __global__ __launch_bounds__(256) void cg_setup_finalize(const double *part, int
     sc->iters = 0;
     sc->done = (out[1] <= sc->tol2) ? 1 : 0;
     sc->alpha = sc->beta = 0.0;
+    sc->restart = 0;
   }
 }
 
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(256) void cg_beta_finalize(const double *part, int6
   if (threadIdx.x == 0) {
     sc->iters += 1;
     sc->rr = out[1];
-    if (out[1] <= sc->tol2 || !(out[0] > 0.0)) {
+    if (out[1] <= sc->tol2 || !(out[0] > 0.0) || sc->iters >= sc->budget) {
       sc->done = 1;
     } else {
       sc->beta = out[0] / sc->rz;
@@ -234,7 +239,70 @@ __global__ __launch_bounds__(256) void residual_finalize(const double *part, int
   if (threadIdx.x == 0) sc->rr = out[0];
 }
 
-__global__ void cast_kernel(const void *src, int src_f32, void *dst, int dst_f32, int64_t n) {
+// The outer loop of a solve, decided on the device after each FP64 residual
+// that follows a finished inner CG (the host only enqueues passes): book the
+// inner iterations, then stop (converged: |r|^2 <= tol2; gave up: iteration
+// limit reached, or an inner solve made no iteration) or ask for a new inner
+// solve with its tolerance -- mixed: max(inner_rtol2 |r|^2, tol2 / 4) on the
+// FP32 correction; FP64: tol2 on CG restarted from the current u -- and its
+// iteration budget.
+__global__ __launch_bounds__(256) void residual_check_finalize(const double *part, int64_t nb, DevScalars *ctl,
+                                                               DevScalars *scm, const DevScalars *gate) {
+  if (gate->done) return;
+  __shared__ double out[1];
+  sum_partials<1>(part, nb, out);
+  if (threadIdx.x == 0) {
+    const int it = scm->iters, pass = ctl->outer - 1;
+    if (pass >= 0 && pass < kMaxPasses) ctl->pass_iters[pass] = it;
+    ctl->iters += it;
+    scm->iters = 0;
+    ctl->rr = out[0];
+    ctl->outer += 1;
+    if (out[0] <= ctl->tol2) {
+      ctl->done = kSolveConverged;
+    } else if (ctl->iters >= ctl->maxit || (pass >= 0 && it == 0)) {
+      ctl->done = kSolveGaveUp;
+    } else {
+      scm->tol2 = ctl->mixed ? fmax(ctl->inner_rtol2 * out[0], 0.25 * ctl->tol2) : ctl->tol2;
+      scm->budget = ctl->maxit - ctl->iters;
+      scm->restart = 1;
+    }
+  }
+}
+
+__global__ void solve_gates_kernel(const DevScalars *ctl, const DevScalars *scm, DevScalars *gR, DevScalars *gF) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    gR->done = (ctl->done || !scm->restart) ? 1 : 0;
+    gF->done = (ctl->done || !scm->done) ? 1 : 0;
+  }
+}
+
+// Start of a solve (ctl->fnorm2 and ctl->tol2 are set): a zero load is
+// solved by u = 0 at once.
+__global__ void solve_init_kernel(DevScalars *ctl, DevScalars *scm, int maxit, double inner_rtol2, int mixed) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->done = ctl->fnorm2 == 0.0 ? kSolveConverged : kSolveRunning;
+    ctl->rr = 0.0;
+    ctl->outer = 0;
+    ctl->iters = 0;
+    ctl->maxit = maxit;
+    ctl->mixed = mixed;
+    ctl->inner_rtol2 = inner_rtol2;
+    for (int q = 0; q < kMaxPasses; ++q) ctl->pass_iters[q] = 0;
+    scm->iters = 0;
+    scm->done = 1;      // no inner CG running: the first FP64 check runs
+    scm->restart = 0;
+    scm->budget = maxit;
+  }
+}
+__global__ void zero_if_no_load_kernel(double *u0, double *u1, double *u2, int64_t n, const DevScalars *ctl) {
+  if (ctl->fnorm2 != 0.0) return;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+    u0[t] = u1[t] = u2[t] = 0.0;
+}
+
+__global__ void cast_kernel(const void *src, int src_f32, void *dst, int dst_f32, int64_t n, const DevScalars *gate) {
+  if (gate && gate->done) return;
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
     const double x = src_f32 ? double(((const float *)src)[t]) : ((const double *)src)[t];
     if (dst_f32) ((float *)dst)[t] = float(x); else ((double *)dst)[t] = x;
@@ -261,9 +329,16 @@ __global__ void extrapolate_kernel(double *u0, double *u1, double *u2, double *v
   }
 }
 
-__global__ void axpy64_kernel(double *y, const float *x, int64_t n) {
+__global__ void axpy64_kernel(double *y, const float *x, int64_t n, const DevScalars *gate) {
+  if (gate && gate->done) return;
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
     y[t] += double(x[t]);
+}
+
+__global__ void zero32_kernel(float *x, int64_t n, const DevScalars *gate) {
+  if (gate && gate->done) return;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x)
+    x[t] = 0.0f;
 }
 
 // Eq. (9) at the centroid: strain B(0) u_e (dN_a/dx = s_ax / (4 hx) there),
@@ -320,12 +395,12 @@ hipError_t launch_mech_rhs(const MechGrid &M, const double *theta, double *f[3],
 
 template <typename T>
 hipError_t launch_cg_setup(const MechGrid &M, const CgVecs<T> &v, const T *rhs[3], double *partials,
-                           DevScalars *sc, hipStream_t s) {
+                           DevScalars *sc, const DevScalars *gate, hipStream_t s) {
   const T *x[3] = {v.u[0], v.u[1], v.u[2]};
-  hipError_t e = launch_hex8<T, 2>(M, x, EpiJacobiStart<T>{v, rhs[0], rhs[1], rhs[2]}, partials, nullptr, s);
+  hipError_t e = launch_hex8<T, 2>(M, x, EpiJacobiStart<T>{v, rhs[0], rhs[1], rhs[2]}, partials, gate, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cg_setup_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
-                     cell_blocks(M.g, cell_kchunk(M.g)), sc);
+                     cell_blocks(M.g, cell_kchunk(M.g)), sc, gate);
   return hipGetLastError();
 }
 
@@ -357,9 +432,9 @@ template hipError_t launch_cg_apply_alpha<double>(const MechGrid &, const CgVecs
 template hipError_t launch_cg_apply_alpha<float>(const MechGrid &, const CgVecs<float> &, double *, DevScalars *,
                                                  hipStream_t);
 template hipError_t launch_cg_setup<double>(const MechGrid &, const CgVecs<double> &, const double *[3], double *,
-                                            DevScalars *, hipStream_t);
+                                            DevScalars *, const DevScalars *, hipStream_t);
 template hipError_t launch_cg_setup<float>(const MechGrid &, const CgVecs<float> &, const float *[3], double *,
-                                           DevScalars *, hipStream_t);
+                                           DevScalars *, const DevScalars *, hipStream_t);
 template hipError_t launch_cg_iteration<double>(const MechGrid &, const CgVecs<double> &, double *, DevScalars *,
                                                 hipStream_t);
 template hipError_t launch_cg_iteration<float>(const MechGrid &, const CgVecs<float> &, double *, DevScalars *,
@@ -375,8 +450,39 @@ hipError_t launch_residual64(const MechGrid &M, const double *f[3], const double
   return hipGetLastError();
 }
 
-hipError_t launch_vec_cast(const void *src, int src_f32, void *dst, int dst_f32, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(cast_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, src, src_f32, dst, dst_f32, n);
+hipError_t launch_residual_check(const MechGrid &M, const double *f[3], const double *u[3], double *r[3],
+                                 double *partials, DevScalars *ctl, DevScalars *scm, const DevScalars *gate,
+                                 hipStream_t s) {
+  hipError_t e =
+      launch_hex8<double, 1>(M, u, EpiResidual64{f[0], f[1], f[2], r[0], r[1], r[2]}, partials, gate, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(residual_check_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
+                     cell_blocks(M.g, cell_kchunk(M.g)), ctl, scm, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_gates(const DevScalars *ctl, const DevScalars *scm, DevScalars *gR, DevScalars *gF,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(solve_gates_kernel, dim3(1), dim3(64), 0, s, ctl, scm, gR, gF);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_init(DevScalars *ctl, DevScalars *scm, int maxit, double inner_rtol2, int mixed,
+                             double *u[3], int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(solve_init_kernel, dim3(1), dim3(64), 0, s, ctl, scm, maxit, inner_rtol2, mixed);
+  hipLaunchKernelGGL(zero_if_no_load_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, u[0], u[1], u[2], n,
+                     (const DevScalars *)ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_cast(const void *src, int src_f32, void *dst, int dst_f32, int64_t n, const DevScalars *gate,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(cast_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, src, src_f32, dst, dst_f32, n, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_vec_zero32(float *x, int64_t n, const DevScalars *gate, hipStream_t s) {
+  hipLaunchKernelGGL(zero32_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, x, n, gate);
   return hipGetLastError();
 }
 
@@ -391,8 +497,8 @@ hipError_t launch_mask_fixed(const MechGrid &M, int c, double *u, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_vec_axpy64(double *y, const float *x, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(axpy64_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, y, x, n);
+hipError_t launch_vec_axpy64(double *y, const float *x, int64_t n, const DevScalars *gate, hipStream_t s) {
+  hipLaunchKernelGGL(axpy64_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, y, x, n, gate);
   return hipGetLastError();
 }
 

@@ -746,7 +746,11 @@ struct EpiStart0 {
 
 // ---- CG with the V-cycle ------------------------------------------------------------
 
-__global__ void cgmg_start_finalize(const double *part, int64_t nb, DevScalars *sc) {
+// Start of an inner CG (a restart of the solve).  With a gate: skipped while
+// the gate says so (the inner CG already running goes on); when it runs, the
+// gate then tells the rest of the setup whether the inner CG has work.
+__global__ void cgmg_start_finalize(const double *part, int64_t nb, DevScalars *sc, DevScalars *gate) {
+  if (gate && gate->done) return;
   __shared__ double out[1];
   sum_partials<1>(part, nb, out);
   if (threadIdx.x == 0) {
@@ -754,6 +758,8 @@ __global__ void cgmg_start_finalize(const double *part, int64_t nb, DevScalars *
     sc->iters = 0;
     sc->done = (out[0] <= sc->tol2) ? 1 : 0;
     sc->alpha = sc->beta = sc->rz = 0.0;
+    sc->restart = 0;
+    if (gate) gate->done = sc->done;
   }
 }
 
@@ -778,8 +784,8 @@ __global__ __launch_bounds__(256) void cgmg_dot_kernel(MechGrid M, CgVecs<T> v, 
 // rz_new = r . z; beta = rz_new / rz (first: none).  A non-positive r . z
 // means the preconditioned residual vanished or M^{-1} lost definiteness:
 // stop; the caller checks the true residual.
-__global__ void cgmg_rz_finalize(const double *part, int64_t nb, DevScalars *sc, int first) {
-  if (sc->done) return;
+__global__ void cgmg_rz_finalize(const double *part, int64_t nb, DevScalars *sc, int first, const DevScalars *gate) {
+  if (gate ? gate->done : sc->done) return;
   __shared__ double out[1];
   sum_partials<1>(part, nb, out);
   if (threadIdx.x == 0) {
@@ -795,8 +801,8 @@ __global__ void cgmg_rz_finalize(const double *part, int64_t nb, DevScalars *sc,
 
 template <typename T>
 __global__ __launch_bounds__(256) void cgmg_p_kernel(CgVecs<T> v, V3<T> z, int64_t ntot, const DevScalars *sc,
-                                                     int first) {
-  if (sc->done) return;
+                                                     int first, const DevScalars *gate) {
+  if (gate ? gate->done : sc->done) return;
   const T beta = T(sc->beta);
   for (int64_t n = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; n < ntot; n += int64_t(gridDim.x) * blockDim.x) {
 #pragma unroll
@@ -834,7 +840,7 @@ __global__ void cgmg_rr_finalize(const double *part, int64_t nb, DevScalars *sc)
   if (threadIdx.x == 0) {
     sc->iters += 1;
     sc->rr = out[0];
-    if (out[0] <= sc->tol2) sc->done = 1;
+    if (out[0] <= sc->tol2 || sc->iters >= sc->budget) sc->done = 1;
   }
 }
 
@@ -964,24 +970,25 @@ hipError_t launch_mg_vcycle(const MgDev<T> &G, V3<T> b, const DevScalars *sc, V3
 
 template <typename T>
 hipError_t launch_cgmg_setup(const MgDev<T> &G, const CgVecs<T> &v, const T *rhs[3], double *partials,
-                             DevScalars *sc, hipStream_t s) {
+                             DevScalars *sc, DevScalars *gate, hipStream_t s) {
   const MgLevel<T> &L0 = G.L[0];
   const int64_t nb = lblocks(L0);
   const int fuse = G.nlev > 1;
   const T *u[3] = {v.u[0], v.u[1], v.u[2]};
   hipError_t e0 = launch_hex8<T, 1>(G.M, u, EpiStart0<T>{v, rhs[0], rhs[1], rhs[2], L0, fuse, T(L0.c2[0])}, partials,
-                                    nullptr, s);
+                                    gate, s);
   if (e0 != hipSuccess) return e0;
   hipLaunchKernelGGL(cgmg_start_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
-                     cell_blocks(G.M.g, cell_kchunk(G.M.g)), sc);
+                     cell_blocks(G.M.g, cell_kchunk(G.M.g)), sc, gate);
+  // the rest of the setup runs only after a restart that left work to do
+  const DevScalars *g2 = gate ? (const DevScalars *)gate : (const DevScalars *)sc;
   V3<T> r{{v.r[0], v.r[1], v.r[2]}}, z;
-  hipError_t e = vcycle_level(G, 0, r, sc, &z, s, fuse != 0);
+  hipError_t e = vcycle_level(G, 0, r, g2, &z, s, fuse != 0);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((cgmg_dot_kernel<T>), lgrid(L0), dim3(BX, BY), 0, s, G.M, v, z, (const DevScalars *)sc,
-                     partials);
-  hipLaunchKernelGGL(cgmg_rz_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc, 1);
+  hipLaunchKernelGGL((cgmg_dot_kernel<T>), lgrid(L0), dim3(BX, BY), 0, s, G.M, v, z, g2, partials);
+  hipLaunchKernelGGL(cgmg_rz_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc, 1, g2);
   hipLaunchKernelGGL((cgmg_p_kernel<T>), dim3(flat_blocks(L0.n)), dim3(256), 0, s, v, z, L0.n,
-                     (const DevScalars *)sc, 1);
+                     (const DevScalars *)sc, 1, g2);
   return hipGetLastError();
 }
 
@@ -1001,8 +1008,10 @@ hipError_t launch_cgmg_iteration(const MgDev<T> &G, const CgVecs<T> &v, double *
   if ((e = vcycle_level(G, 0, r, sc, &z, s, fuse != 0)) != hipSuccess) return e;
   hipLaunchKernelGGL((cgmg_dot_kernel<T>), lgrid(L0), dim3(BX, BY), 0, s, G.M, v, z, (const DevScalars *)sc,
                      partials);
-  hipLaunchKernelGGL(cgmg_rz_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc, 0);
-  hipLaunchKernelGGL((cgmg_p_kernel<T>), dim3(fb), dim3(256), 0, s, v, z, L0.n, (const DevScalars *)sc, 0);
+  hipLaunchKernelGGL(cgmg_rz_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc, 0,
+                     (const DevScalars *)nullptr);
+  hipLaunchKernelGGL((cgmg_p_kernel<T>), dim3(fb), dim3(256), 0, s, v, z, L0.n, (const DevScalars *)sc, 0,
+                     (const DevScalars *)nullptr);
   return hipGetLastError();
 }
 
@@ -1011,7 +1020,7 @@ hipError_t launch_cgmg_iteration(const MgDev<T> &G, const CgVecs<T> &v, double *
   template hipError_t launch_mg_power<T>(const MgDev<T> &, int, int, double *, hipStream_t);               \
   template hipError_t launch_mg_vcycle<T>(const MgDev<T> &, V3<T>, const DevScalars *, V3<T> *, hipStream_t); \
   template hipError_t launch_cgmg_setup<T>(const MgDev<T> &, const CgVecs<T> &, const T *[3], double *,    \
-                                           DevScalars *, hipStream_t);                                     \
+                                           DevScalars *, DevScalars *, hipStream_t);                       \
   template hipError_t launch_cgmg_iteration<T>(const MgDev<T> &, const CgVecs<T> &, double *, DevScalars *, \
                                                hipStream_t);
 ETM_MG_INST(double)

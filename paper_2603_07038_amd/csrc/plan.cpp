@@ -449,6 +449,14 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   take(p->r_psum, N * 8);
   take(p->r_part, size_t(std::max<int64_t>(p->nblocks_node, 1024)) * kRedWidth * 8);
   take(p->r_sc, sizeof(DevScalars));
+  // the mechanical solve owns its partials, scalars and temperature copy, so
+  // that it can run beside the march on another stream
+  take(p->r_partm, size_t(std::max<int64_t>(p->nblocks_node, 1024)) * kRedWidth * 8);
+  take(p->r_scm, sizeof(DevScalars));
+  take(p->r_ctl, sizeof(DevScalars));
+  take(p->r_gR, sizeof(DevScalars));
+  take(p->r_gF, sizeof(DevScalars));
+  take(p->r_thsolve, N * 8);
   take(p->r_hist, size_t(p->hist_cap) * p->hist_cols * 8);
   for (int c = 0; c < 3; ++c) {
     take(p->r_u64[c], N * 8); take(p->r_f64[c], N * 8); take(p->r_r64[c], N * 8); take(p->r_dinv64[c], N * 8);
@@ -741,47 +749,6 @@ etm_status poll_scalars(etm_plan *p) {
   return ETM_OK;
 }
 
-etm_status set_tol2(etm_plan *p, double tol2) {
-  p->sc_host->tol2 = tol2;
-  HIP_TRY(hipMemcpyAsync(&p->sc()->tol2, &p->sc_host->tol2, sizeof(double), hipMemcpyHostToDevice, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  return ETM_OK;
-}
-
-template <typename T>
-etm_status run_cg(etm_plan *p, const MechGrid &M, const CgVecs<T> &v, const T *rhs[3], int zero_init, int budget,
-                  int *iters) {
-  etm_status st;
-  (void)zero_init;
-  HIP_TRY(launch_cg_setup<T>(M, v, rhs, p->ptr<double>(p->r_part), p->sc(), p->stream));
-  *iters = 0;
-  const int chunk = 32;
-  for (;;) {
-    if ((st = poll_scalars(p)) != ETM_OK) return st;
-    *iters = p->sc_host->iters;
-    if (p->sc_host->done || *iters >= budget) break;
-    const int n = std::min(chunk, budget - *iters);
-    for (int q = 0; q < n; ++q) HIP_TRY(launch_cg_iteration<T>(M, v, p->ptr<double>(p->r_part), p->sc(), p->stream));
-  }
-  return ETM_OK;
-}
-
-template <typename T>
-etm_status run_cgmg(etm_plan *p, const MgDev<T> &G, const CgVecs<T> &v, const T *rhs[3], int budget, int *iters) {
-  etm_status st;
-  HIP_TRY(launch_cgmg_setup<T>(G, v, rhs, p->ptr<double>(p->r_part), p->sc(), p->stream));
-  *iters = 0;
-  const int chunk = 8;
-  for (;;) {
-    if ((st = poll_scalars(p)) != ETM_OK) return st;
-    *iters = p->sc_host->iters;
-    if (p->sc_host->done || *iters >= budget) break;
-    const int n = std::min(chunk, budget - *iters);
-    for (int q = 0; q < n; ++q) HIP_TRY(launch_cgmg_iteration<T>(G, v, p->ptr<double>(p->r_part), p->sc(), p->stream));
-  }
-  return ETM_OK;
-}
-
 template <typename T>
 MgDev<T> mg_dev(const etm_plan *p) {
   MgDev<T> G{};
@@ -955,7 +922,7 @@ template <typename T>
 etm_status mg_setup(etm_plan *p) {
   MgDev<T> G = mg_dev<T>(p);
   HIP_TRY(launch_mg_build<T>(G, p->stream));
-  double *part = p->ptr<double>(p->r_part);
+  double *part = p->ptr<double>(p->r_partm);
   for (int l = 0; l + 1 < G.nlev; ++l) HIP_TRY(launch_mg_power<T>(G, l, kMgPowerIters, part, p->stream));
   const MgHostLevel &H = p->mg.back();
   std::vector<double> lam(kMgMaxLevels, 0.0);
@@ -983,8 +950,88 @@ etm_status mg_setup(etm_plan *p) {
 
 }  // namespace
 
+namespace {
+
+// One enqueue group of a solve: n_pass passes of iters[q] inner CG
+// iterations each, then von Mises, the copy of the control block to pinned
+// host memory and the completion event.  A pass is
+//   [restart phase] (re)start an inner CG -- only when the device's last
+//       FP64 check asked for one: mixed, K c = r64 in FP32 from c = 0 (the
+//       iterative-refinement correction); FP64, CG on K u = f from the
+//       current u;
+//   iters[q] inner iterations (no-ops once the inner CG has finished);
+//   [finish phase] once the inner CG has finished: mixed, u64 += c; the FP64
+//       residual check that decides the solve or asks for a restart.
+// An inner CG still running at the end of a pass goes on in the next one.
+// Every kernel is a no-op once the device has decided the solve.
+template <typename T>
+etm_status enqueue_passes(etm_plan *p, int n_pass, const int *iters) {
+  const MechGrid M = p->mech_grid();
+  const int64_t N = p->ntot;
+  const bool mixed = sizeof(T) == 4;
+  const bool use_mg = !p->mg.empty();
+  double *u64[3], *f64[3], *r64[3];
+  for (int c = 0; c < 3; ++c) {
+    u64[c] = p->ptr<double>(p->r_u64[c]); f64[c] = p->ptr<double>(p->r_f64[c]); r64[c] = p->ptr<double>(p->r_r64[c]);
+  }
+  const double *cf64[3] = {f64[0], f64[1], f64[2]};
+  const double *cu64[3] = {u64[0], u64[1], u64[2]};
+  DevScalars *scm = p->scm(), *ctl = p->ctl(), *gR = p->ptr<DevScalars>(p->r_gR), *gF = p->ptr<DevScalars>(p->r_gF);
+  double *part = p->ptr<double>(p->r_partm);
+  CgVecs<T> v;
+  const T *rhs[3];
+  for (int c = 0; c < 3; ++c) {
+    if (mixed) {
+      v.u[c] = (T *)p->ptr<float>(p->r_u32[c]); v.r[c] = (T *)p->ptr<float>(p->r_r32[c]);
+      v.p[c] = (T *)p->ptr<float>(p->r_p32[c]); v.w[c] = (T *)p->ptr<float>(p->r_w32[c]);
+      v.dinv[c] = (const T *)p->ptr<float>(p->r_dinv32[c]);
+      rhs[c] = (const T *)p->ptr<float>(p->r_rhs32[c]);
+    } else {
+      v.u[c] = (T *)u64[c]; v.r[c] = (T *)r64[c];
+      v.p[c] = (T *)p->ptr<double>(p->r_p64[c]); v.w[c] = (T *)p->ptr<double>(p->r_w64[c]);
+      v.dinv[c] = (const T *)p->ptr<double>(p->r_dinv64[c]);
+      rhs[c] = (const T *)f64[c];
+    }
+  }
+  const MgDev<T> G = use_mg ? mg_dev<T>(p) : MgDev<T>{};
+  for (int q = 0; q < n_pass; ++q) {
+    HIP_TRY(launch_solve_gates(ctl, scm, gR, gF, p->stream));
+    if (mixed)
+      for (int c = 0; c < 3; ++c) {
+        HIP_TRY(launch_vec_cast(r64[c], 0, (void *)rhs[c], 1, N, gR, p->stream));
+        HIP_TRY(launch_vec_zero32((float *)v.u[c], N, gR, p->stream));
+      }
+    if (use_mg) HIP_TRY(launch_cgmg_setup<T>(G, v, rhs, part, scm, gR, p->stream));
+    else HIP_TRY(launch_cg_setup<T>(M, v, rhs, part, scm, gR, p->stream));
+    for (int it = 0; it < iters[q]; ++it) {
+      if (use_mg) HIP_TRY(launch_cgmg_iteration<T>(G, v, part, scm, p->stream));
+      else HIP_TRY(launch_cg_iteration<T>(M, v, part, scm, p->stream));
+    }
+    HIP_TRY(launch_solve_gates(ctl, scm, gR, gF, p->stream));
+    if (mixed)
+      for (int c = 0; c < 3; ++c) HIP_TRY(launch_vec_axpy64(u64[c], (const float *)v.u[c], N, gF, p->stream));
+    HIP_TRY(launch_residual_check(M, cf64, cu64, r64, part, ctl, scm, gF, p->stream));
+  }
+  HIP_TRY(launch_von_mises(M, p->ptr<double>(p->r_thsolve), cu64, p->ptr<double>(p->r_vm), p->stream));
+  HIP_TRY(hipMemcpyAsync(p->ctl_host, ctl, sizeof(DevScalars), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipEventRecord(p->ev_solve, p->stream));
+  return ETM_OK;
+}
+
+etm_status enqueue_passes_any(etm_plan *p, int n_pass, const int *iters) {
+  return p->prec == ETM_PREC_FP64 ? enqueue_passes<double>(p, n_pass, iters) : enqueue_passes<float>(p, n_pass, iters);
+}
+
+}  // namespace
+
+// Enqueue a mechanical solve of Eq. (8) for the current temperature and the
+// von Mises stress of Eq. (9) on the plan's stream; returns without waiting
+// (apart from the first solve of a plan, which builds the multigrid
+// hierarchy).  The passes enqueued follow the previous solve's iteration
+// counts; solve_settle adds more if the device has not decided the solve.
 etm_status mech_solve_impl(etm_plan *p) {
   etm_status st;
+  if ((st = solve_settle(p)) != ETM_OK) return st;  // the previous solve owns u and the scalars
   const MechGrid M = p->mech_grid();
   const int64_t N = p->ntot;
   double *u64[3], *f64[3], *r64[3], *dinv64[3];
@@ -1000,7 +1047,8 @@ etm_status mech_solve_impl(etm_plan *p) {
   if (!p->dinv_ready) {
     HIP_TRY(launch_mech_diag(M, dinv64, p->stream));
     if (p->prec == ETM_PREC_MIXED)
-      for (int c = 0; c < 3; ++c) HIP_TRY(launch_vec_cast(dinv64[c], 0, p->ptr<float>(p->r_dinv32[c]), 1, N, p->stream));
+      for (int c = 0; c < 3; ++c)
+        HIP_TRY(launch_vec_cast(dinv64[c], 0, p->ptr<float>(p->r_dinv32[c]), 1, N, nullptr, p->stream));
     p->dinv_ready = true;
   }
   // Initial guess: the last solution, extrapolated linearly in time through
@@ -1016,83 +1064,80 @@ etm_status mech_solve_impl(etm_plan *p) {
     HIP_TRY(launch_extrapolate(u64, uprev, sc, N, p->stream));
   }
   if (tn != p->sol_t[0]) { p->sol_t[1] = p->sol_t[0]; p->sol_t[0] = tn; }
+  // the solve's own copy of the temperature (von Mises reads it at the end)
   const double *theta = p->ptr<double>(p->r_theta[p->th_cur]);
-  HIP_TRY(launch_mech_rhs(M, theta, f64, p->ptr<double>(p->r_part), p->sc(), p->opts.cg_rtol, p->stream));
-  if ((st = poll_scalars(p)) != ETM_OK) return st;
-  const double fn2 = p->sc_host->fnorm2, target2 = p->opts.cg_rtol * p->opts.cg_rtol * fn2;
-  const int maxit = p->opts.cg_maxit;
-  int total = 0, outer = 0;
-  double rr = 0;
-  bool conv = false;
+  HIP_TRY(hipMemcpyAsync(p->ptr<double>(p->r_thsolve), theta, size_t(N) * 8, hipMemcpyDeviceToDevice, p->stream));
+  HIP_TRY(launch_mech_rhs(M, theta, f64, p->ptr<double>(p->r_partm), p->ctl(), p->opts.cg_rtol, p->stream));
+  HIP_TRY(hipEventRecord(p->ev_copy, p->stream));  // the temperature is no longer read after this
+  const double inner_rtol = 1e-5;
+  HIP_TRY(launch_solve_init(p->ctl(), p->scm(), p->opts.cg_maxit, inner_rtol * inner_rtol,
+                            p->prec == ETM_PREC_MIXED ? 1 : 0, u64, N, p->stream));
   const double *cf64[3] = {f64[0], f64[1], f64[2]};
   const double *cu64[3] = {u64[0], u64[1], u64[2]};
-  if (fn2 == 0.0) {
-    for (int c = 0; c < 3; ++c) HIP_TRY(launch_fill(u64[c], N * 8, p->stream));
-    conv = true;
-  } else if (p->prec == ETM_PREC_FP64) {
-    CgVecs<double> v;
-    for (int c = 0; c < 3; ++c) {
-      v.u[c] = u64[c]; v.r[c] = r64[c]; v.p[c] = p->ptr<double>(p->r_p64[c]); v.w[c] = p->ptr<double>(p->r_w64[c]);
-      v.dinv[c] = dinv64[c];
-    }
-    while (total < maxit) {
-      if ((st = set_tol2(p, target2)) != ETM_OK) return st;
-      int it = 0;
-      st = use_mg ? run_cgmg<double>(p, mg_dev<double>(p), v, cf64, maxit - total, &it)
-                  : run_cg<double>(p, M, v, cf64, 0, maxit - total, &it);
-      if (st != ETM_OK) return st;
-      total += it;
-      // true residual
-      HIP_TRY(launch_residual64(M, cf64, cu64, r64, p->ptr<double>(p->r_part), p->sc(), p->stream));
-      ++outer;
-      if ((st = poll_scalars(p)) != ETM_OK) return st;
-      rr = p->sc_host->rr;
-      if (rr <= target2) { conv = true; break; }
-      if (it == 0) break;
-    }
+  DevScalars *gR = p->ptr<DevScalars>(p->r_gR), *gF = p->ptr<DevScalars>(p->r_gF);
+  HIP_TRY(launch_solve_gates(p->ctl(), p->scm(), gR, gF, p->stream));
+  HIP_TRY(launch_residual_check(M, cf64, cu64, r64, p->ptr<double>(p->r_partm), p->ctl(), p->scm(), gF,
+                                p->stream));
+  // passes as the last solve needed them (a first solve: a few of a typical length)
+  int iters[kMaxPasses];
+  int n_pass = p->pass_plan_n;
+  if (n_pass <= 0) {
+    n_pass = p->prec == ETM_PREC_MIXED ? 3 : 1;
+    for (int q = 0; q < n_pass; ++q) iters[q] = p->prec == ETM_PREC_MIXED ? 16 : 48;
   } else {
-    // iterative refinement: FP64 residual, FP32 Jacobi-PCG correction
-    CgVecs<float> v;
-    const float *rhs32[3];
-    for (int c = 0; c < 3; ++c) {
-      v.u[c] = p->ptr<float>(p->r_u32[c]); v.r[c] = p->ptr<float>(p->r_r32[c]); v.p[c] = p->ptr<float>(p->r_p32[c]);
-      v.w[c] = p->ptr<float>(p->r_w32[c]); v.dinv[c] = p->ptr<float>(p->r_dinv32[c]);
-      rhs32[c] = p->ptr<float>(p->r_rhs32[c]);
-    }
-    const double inner_rtol = 1e-5;
-    for (outer = 0; outer < 50;) {
-      HIP_TRY(launch_residual64(M, cf64, cu64, r64, p->ptr<double>(p->r_part), p->sc(), p->stream));
-      ++outer;
-      if ((st = poll_scalars(p)) != ETM_OK) return st;
-      rr = p->sc_host->rr;
-      if (rr <= target2) { conv = true; break; }
-      if (total >= maxit) break;
-      for (int c = 0; c < 3; ++c) {
-        HIP_TRY(launch_vec_cast(r64[c], 0, (void *)rhs32[c], 1, N, p->stream));
-        HIP_TRY(launch_fill(v.u[c], N * 4, p->stream));
-      }
-      if ((st = set_tol2(p, std::max(inner_rtol * inner_rtol * rr, 0.25 * target2))) != ETM_OK) return st;
-      int it = 0;
-      st = use_mg ? run_cgmg<float>(p, mg_dev<float>(p), v, rhs32, maxit - total, &it)
-                  : run_cg<float>(p, M, v, rhs32, 1, maxit - total, &it);
-      if (st != ETM_OK) return st;
-      total += it;
-      for (int c = 0; c < 3; ++c) HIP_TRY(launch_vec_axpy64(u64[c], v.u[c], N, p->stream));
-      if (it == 0) break;
-    }
+    for (int q = 0; q < n_pass; ++q) iters[q] = p->pass_plan[q];
   }
-  HIP_TRY(launch_von_mises(M, theta, cu64, p->ptr<double>(p->r_vm), p->stream));
-  p->cg_iters = total;
-  p->cg_outer = outer;
-  p->cg_total += total;
-  p->cg_relres = fn2 > 0 ? std::sqrt(rr / fn2) : 0.0;
+  if ((st = enqueue_passes_any(p, n_pass, iters)) != ETM_OK) return st;
+  p->solve_enqueued = 0;
+  for (int q = 0; q < n_pass; ++q) p->solve_enqueued += iters[q];
+  p->solve_pending = true;
   p->n_solves++;
-  if (!conv) {
-    if (p->host_status == ETM_OK) p->host_status = ETM_E_NOCONV;
-    return fail(ETM_E_NOCONV, "mechanical CG did not converge: relres " + std::to_string(p->cg_relres) + " after " +
-                                  std::to_string(total) + " iterations");
-  }
   return ETM_OK;
+}
+
+// Wait for the pending solve (through its event and the pinned copy of the
+// control block), adding passes while the device has not decided it;
+// record its counts and plan the next solve's passes.  A solve that gave up
+// sets ETM_E_NOCONV, reported by etm_sync; only HIP errors are returned.
+etm_status solve_settle(etm_plan *p) {
+  if (!p->solve_pending) return ETM_OK;
+  for (;;) {
+    HIP_TRY(hipEventSynchronize(p->ev_solve));
+    const DevScalars c = *p->ctl_host;
+    if (c.done == kSolveRunning) {
+      // more passes, on the plan's stream after what was enqueued: as many
+      // iterations again as so far (at least 32), so that a long solve needs
+      // few of these round trips
+      HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_solve, 0));
+      const int add = std::max(32, p->solve_enqueued);
+      const int more[2] = {add / 2, add - add / 2};
+      etm_status st = enqueue_passes_any(p, 2, more);
+      if (st != ETM_OK) {
+        p->solve_pending = false;
+        return st;
+      }
+      p->solve_enqueued += add;
+      continue;
+    }
+    p->solve_pending = false;
+    p->cg_iters = c.iters;
+    p->cg_outer = c.outer;
+    p->cg_total += c.iters;
+    p->cg_relres = c.fnorm2 > 0 ? std::sqrt(c.rr / c.fnorm2) : 0.0;
+    // the next solve's passes: each a little longer than this solve's
+    int n = 0;
+    for (int q = 0; q + 1 < c.outer && q < kMaxPasses; ++q) {
+      if (c.pass_iters[q] <= 0) break;
+      p->pass_plan[n++] = c.pass_iters[q] + c.pass_iters[q] / 4 + 2;
+    }
+    if (c.done == kSolveConverged && n > 0) p->pass_plan_n = n;
+    if (c.done != kSolveConverged && p->host_status == ETM_OK) {
+      p->host_status = ETM_E_NOCONV;
+      p->host_msg = "mechanical CG did not converge: relres " + std::to_string(p->cg_relres) + " after " +
+                    std::to_string(c.iters) + " iterations";
+    }
+    return ETM_OK;
+  }
 }
 
 }  // namespace etm
@@ -1178,11 +1223,18 @@ etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(ETM_E_INVAL, "workspace must be 256-byte aligned");
   p->ws = static_cast<char *>(ws);
   p->stream = static_cast<hipStream_t>(stream);
+  if (p->solve_pending) {  // a solve of the previous binding still writes its control block
+    HIP_TRY(hipEventSynchronize(p->ev_solve));
+    p->solve_pending = false;
+  }
   if (!p->mstream) HIP_TRY(hipStreamCreateWithFlags(&p->mstream, hipStreamNonBlocking));
   if (!p->ev_main) HIP_TRY(hipEventCreateWithFlags(&p->ev_main, hipEventDisableTiming));
-  if (!p->ev_mech) HIP_TRY(hipEventCreateWithFlags(&p->ev_mech, hipEventDisableTiming));
+  if (!p->ev_copy) HIP_TRY(hipEventCreateWithFlags(&p->ev_copy, hipEventDisableTiming));
+  if (!p->ev_solve) HIP_TRY(hipEventCreateWithFlags(&p->ev_solve, hipEventDisableTiming));
   if (!p->sc_host) HIP_TRY(hipHostMalloc((void **)&p->sc_host, sizeof(DevScalars), hipHostMallocDefault));
+  if (!p->ctl_host) HIP_TRY(hipHostMalloc((void **)&p->ctl_host, sizeof(DevScalars), hipHostMallocDefault));
   std::memset(p->sc_host, 0, sizeof(DevScalars));
+  std::memset(p->ctl_host, 0, sizeof(DevScalars));
   HIP_TRY(launch_fill(p->ws, int64_t(p->footprint), p->stream));
   auto up = [&](const Region &r, const void *src, size_t n) -> etm_status {
     if (n) HIP_TRY(hipMemcpyAsync(p->ws + r.off, src, n, hipMemcpyHostToDevice, p->stream));
@@ -1212,9 +1264,11 @@ etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
   p->n_solves = 0; p->cg_iters = 0; p->cg_outer = 0; p->cg_total = 0; p->cg_relres = 0;
   p->sol_t[0] = p->sol_t[1] = -1;
   p->host_status = ETM_OK;
+  p->host_msg.clear();
   p->dinv_ready = false;
   p->mg_ready = false;
   p->joule_pending = false;
+  p->pass_plan_n = 0;
   return ETM_OK;
 }
 
@@ -1258,15 +1312,16 @@ etm_status etm_advance(etm_plan *p, int64_t n) {
             if (allowed <= 0) break;
             if ((st = march(allowed)) != ETM_OK) return st;
           }
-          // The solve on the side stream, after the thermal step; the plan's
-          // stream waits for it before any later work.
+          // The solve on the side stream, after the thermal step.  It owns
+          // its vectors, scalars and a copy of the temperature, so the
+          // plan's stream waits only until that copy is taken (the next
+          // thermal step may not overwrite the temperature before).
           HIP_TRY(hipStreamWaitEvent(p->mstream, p->ev_main, 0));
           hipStream_t main_stream = p->stream;
           p->stream = p->mstream;
           st = mech_solve_impl(p);
           p->stream = main_stream;
-          HIP_TRY(hipEventRecord(p->ev_mech, p->mstream));
-          HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_mech, 0));
+          HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_copy, 0));
         } else {
           st = mech_solve_impl(p);
         }
@@ -1287,7 +1342,8 @@ etm_status etm_mech_solve(etm_plan *p) {
 etm_status etm_sync(etm_plan *p, etm_run_info *info) {
   if (!p) return fail(ETM_E_INVAL, "null plan");
   if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
-  etm_status st = poll_scalars(p);
+  etm_status st = solve_settle(p);
+  if (st == ETM_OK) st = poll_scalars(p);
   if (st != ETM_OK) return st;
   const DevScalars &s = *p->sc_host;
   if (info) {
@@ -1305,13 +1361,17 @@ etm_status etm_sync(etm_plan *p, etm_run_info *info) {
     info->reserved = 0;
   }
   if (s.status != ETM_OK) return fail(s.status, "non-finite field detected on the device");
-  if (p->host_status != ETM_OK) return fail(p->host_status, "mechanical solve did not converge");
+  if (p->host_status != ETM_OK) return fail(p->host_status, p->host_msg);
   return ETM_OK;
 }
 
 etm_status etm_read(const etm_plan *p, int32_t field, void *dst, size_t bytes, int32_t dst_is_device) {
   if (!p || !dst) return fail(ETM_E_INVAL, "null argument");
   if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  {  // a pending solve writes u, von Mises and f: let it finish (its outcome is reported by etm_sync)
+    etm_status s0 = solve_settle(const_cast<etm_plan *>(p));
+    if (s0 != ETM_OK) return s0;
+  }
   if (field < ETM_FIELD_EX || field > ETM_FIELD_FZ) return fail(ETM_E_INVAL, "unknown field");
   const FieldDesc fd = field_shape(p, field);
   const size_t need = size_t(fd.ni) * fd.nj * fd.nk * 8;
@@ -1330,6 +1390,10 @@ etm_status etm_read(const etm_plan *p, int32_t field, void *dst, size_t bytes, i
 etm_status etm_write(etm_plan *p, int32_t field, const void *src, size_t bytes, int32_t src_is_device) {
   if (!p || !src) return fail(ETM_E_INVAL, "null argument");
   if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  {
+    etm_status s0 = solve_settle(p);
+    if (s0 != ETM_OK) return s0;
+  }
   if (field < ETM_FIELD_EX || field > ETM_FIELD_UZ || field == ETM_FIELD_VM)
     return fail(ETM_E_INVAL, "field is not writable");
   if (p->prec == ETM_PREC_MIXED && field >= ETM_FIELD_EX && field <= ETM_FIELD_EZ_PREV)
@@ -1421,6 +1485,10 @@ etm_status etm_checkpoint_size(const etm_plan *p, size_t *bytes) {
 etm_status etm_checkpoint(const etm_plan *p, void *dst, size_t bytes) {
   if (!p || !dst) return fail(ETM_E_INVAL, "null argument");
   if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  {
+    etm_status s0 = solve_settle(const_cast<etm_plan *>(p));
+    if (s0 != ETM_OK) return s0;
+  }
   size_t need = 0;
   etm_checkpoint_size(p, &need);
   if (bytes < need) return fail(ETM_E_NOMEM, "checkpoint buffer too small");
@@ -1440,6 +1508,10 @@ etm_status etm_checkpoint(const etm_plan *p, void *dst, size_t bytes) {
 etm_status etm_restore(etm_plan *p, const void *src, size_t bytes) {
   if (!p || !src) return fail(ETM_E_INVAL, "null argument");
   if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
+  {
+    etm_status s0 = solve_settle(p);
+    if (s0 != ETM_OK) return s0;
+  }
   size_t need = 0;
   etm_checkpoint_size(p, &need);
   if (bytes < need) return fail(ETM_E_INVAL, "checkpoint too small");
@@ -1463,11 +1535,14 @@ etm_status etm_restore(etm_plan *p, const void *src, size_t bytes) {
 
 void etm_plan_destroy(etm_plan *p) {
   if (!p) return;
+  if (p->solve_pending && p->ev_solve) (void)hipEventSynchronize(p->ev_solve);  // its copy targets ctl_host
   if (p->mstream) (void)hipStreamSynchronize(p->mstream);
   if (p->ev_main) (void)hipEventDestroy(p->ev_main);
-  if (p->ev_mech) (void)hipEventDestroy(p->ev_mech);
+  if (p->ev_copy) (void)hipEventDestroy(p->ev_copy);
+  if (p->ev_solve) (void)hipEventDestroy(p->ev_solve);
   if (p->mstream) (void)hipStreamDestroy(p->mstream);
   if (p->sc_host) (void)hipHostFree(p->sc_host);
+  if (p->ctl_host) (void)hipHostFree(p->ctl_host);
   delete p;
 }
 

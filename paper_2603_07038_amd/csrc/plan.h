@@ -76,6 +76,8 @@ struct etm_plan {
   Region r_K[3];        // MIXED: per-edge correction of the leapfrog form for sigma changes
   Region r_elo;         // MIXED: 8-bit residual of e (3 components at stride comp_stride)
   Region r_theta[2], r_theta32, r_psum, r_part, r_sc, r_hist;
+  Region r_partm, r_scm, r_ctl, r_thsolve;  // the mechanical solve's partials, scalars, control block, temperature
+  Region r_gR, r_gF;                        // its gate words (restart phase, finish phase)
   Region r_u64[3], r_f64[3], r_r64[3], r_p64[3], r_w64[3], r_dinv64[3], r_uprev64[3];
   Region r_u32[3], r_r32[3], r_p32[3], r_w32[3], r_dinv32[3], r_rhs32[3];
   Region r_vm, r_stage;
@@ -90,11 +92,18 @@ struct etm_plan {
   char *ws = nullptr;
   hipStream_t stream = nullptr;
   // side stream of overlapped mechanical solves, and the events that order
-  // it against the plan's stream (created at the first bind)
+  // it against the plan's stream (created at the first bind): ev_main after
+  // a thermal step, ev_copy once a solve has read the temperature, ev_solve
+  // at the end of a solve's last enqueued passes
   hipStream_t mstream = nullptr;
-  hipEvent_t ev_main = nullptr, ev_mech = nullptr;
+  hipEvent_t ev_main = nullptr, ev_copy = nullptr, ev_solve = nullptr;
   bool bound = false;
-  DevScalars *sc_host = nullptr;  // pinned
+  DevScalars *sc_host = nullptr;   // pinned
+  DevScalars *ctl_host = nullptr;  // pinned copy of the solve's control block (written by the device)
+  bool solve_pending = false;      // a solve is enqueued and not yet settled
+  int solve_enqueued = 0;          // inner iterations enqueued for it so far
+  int pass_plan_n = 0;             // passes to enqueue for the next solve (0: no history yet)
+  int pass_plan[kMaxPasses] = {};  // inner iterations of each
   int64_t step = 0;
   int cur = 0;      // FP64: e^n = buffer cur; MIXED: set cur
   int th_cur = 0;
@@ -105,6 +114,7 @@ struct etm_plan {
   int64_t cg_total = 0;
   double cg_relres = 0;
   etm_status host_status = ETM_OK;
+  std::string host_msg;
   bool dinv_ready = false;
   bool joule_pending = false;  // Joule power of the current field not yet in psum
   int kchunk = 0;              // z planes per EM block (0 = automatic)
@@ -159,6 +169,8 @@ struct etm_plan {
     return m;
   }
   DevScalars *sc() const { return ptr<DevScalars>(r_sc); }
+  DevScalars *scm() const { return ptr<DevScalars>(r_scm); }
+  DevScalars *ctl() const { return ptr<DevScalars>(r_ctl); }
   int64_t nidx(int i, int j, int k) const { return int64_t(k) * sz + int64_t(j) * sy + i; }
 };
 
@@ -173,5 +185,9 @@ etm_status thermal_one(etm_plan *p);
 etm_status joule_flush(etm_plan *p);
 etm_status coef_refresh(etm_plan *p, bool update_k);
 etm_status diag_record(etm_plan *p, int old_cur);
+// Enqueue a mechanical solve (no wait once the multigrid hierarchy exists).
 etm_status mech_solve_impl(etm_plan *p);
+// Wait for an enqueued solve to be decided (adding passes if it needs more);
+// a solve that gave up sets host_status = ETM_E_NOCONV.
+etm_status solve_settle(etm_plan *p);
 }  // namespace etm

@@ -29,7 +29,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from . import ETM_FIELD_THETA, ETM_FIELD_VM, ETM_PREC_MIXED, Batch, EtmError, Plan, cfl_dt
+from . import ETM_FIELD_THETA, ETM_FIELD_VM, ETM_PREC_MIXED, STATUS_NAMES, Batch, EtmError, Plan, cfl_dt
 
 
 @dataclasses.dataclass
@@ -115,8 +115,8 @@ class Server:
         time, error message or "")."""
         err = ""
         try:
-            plan.mech_solve()
-        except EtmError as e:   # e.g. ETM_E_NOCONV: this request fails, the others go on
+            plan.mech_solve()   # enqueues; its outcome (e.g. ETM_E_NOCONV) comes from etm_sync
+        except EtmError as e:
             err = str(e)
         info = plan.sync(raise_on_error=False)
         theta = plan.read(ETM_FIELD_THETA)
@@ -142,7 +142,7 @@ class Server:
             try:
                 info, theta, vm, finished, err = fut.result()
                 if not err and info["status"] != 0:
-                    err = f"asynchronous status {info['status']}"
+                    err = f"{STATUS_NAMES.get(info['status'], info['status'])}: reported by etm_sync"
                 done.append(Result(rid=req.rid, name=req.prob.name, cells=req.prob.n_cells,
                                    em_steps=req.prob.n_em_steps, arrival=req.arrival, admitted=admitted,
                                    finished=finished, theta_max=float(theta.max()), vm_max=float(vm.max()),

@@ -1,5 +1,6 @@
 """Failure handling, forced from the host so that every kernel still exits
-normally: a mechanical solve stopped at cg_maxit = 1 reports ETM_E_NOCONV,
+normally: a mechanical solve stopped at cg_maxit = 1 reports ETM_E_NOCONV
+at etm_sync,
 a non-finite temperature or field trips the device watchdog (ETM_E_UNSTABLE
 at etm_sync), the server answers an over-budget request with a rejection
 and a non-converging one with an error while the other requests finish,
@@ -27,9 +28,7 @@ def test_cg_maxit_one_reports_noconv(prec):
     plan = _plan(prob, 8, precision=prec, cg_maxit=1)
     th = np.random.default_rng(21).uniform(0, 30, (prob.nz + 1, prob.ny + 1, prob.nx + 1))
     plan.write(etm.ETM_FIELD_THETA, th)
-    with pytest.raises(etm.EtmError) as ei:
-        plan.mech_solve()
-    assert ei.value.status == etm.ETM_E_NOCONV
+    plan.mech_solve()                     # enqueue only: the outcome is reported by etm_sync
     info = plan.sync(raise_on_error=False)
     assert info["status"] == etm.ETM_E_NOCONV and info["cg_iters"] <= 1 and info["cg_relres"] > prob.cg_rtol
     with pytest.raises(etm.EtmError) as ei:
