@@ -89,10 +89,12 @@ def parse():
     ap.add_argument("--batch-variants", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-rates", default="2")
-    ap.add_argument("--probe", choices=["em", "em-fp64", "em-slice", "em-slice-fp64", "mech", "copy"], default=None,
+    ap.add_argument("--probe", choices=["em", "em-fp64", "em-slice", "em-slice-fp64", "mech", "copy", "r1", "r1-fp64"],
+                    default=None,
                     help="short runs for hardware-counter profiles: 8 EM steps of the package (em, em-fp64) or the "
-                         "slice (em-slice*), two slice coupling blocks with their mechanical solves (mech), or a "
-                         "plain 2 GiB device copy (the calibration kernel for FETCH_SIZE / WRITE_SIZE)")
+                         "slice (em-slice*), 8 coupled steps of the package at R = 1 (r1, r1-fp64), two slice "
+                         "coupling blocks with their mechanical solves (mech), or a plain 2 GiB device copy (the "
+                         "calibration kernel for FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -127,7 +129,7 @@ def probe(kind):
         return
     prob = W.config2() if kind.startswith("em-slice") else W.config3()
     prob.mech_every_thermal = 0
-    prob.em_per_thermal = 100000  # no thermal step inside the probe
+    prob.em_per_thermal = 1 if kind.startswith("r1") else 100000  # else no thermal step inside the probe
     prob.history_stride = 0
     dt = etm.cfl_dt(prob)
     J = prob.sample_J_half(dt, 16)

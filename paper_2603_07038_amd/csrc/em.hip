@@ -205,6 +205,46 @@ struct GTh {
   __device__ __forceinline__ double operator()(int di, int dj, int dk) const { return double(th[n + di + dj * sy + dk * sz]); }
 };
 
+// The per-material EM constants in LDS: eps_r, the scaled conductance
+// (stored negated where sigma depends on T, so one load gives both) and the
+// temperature coefficient.  Loaded once per block; every thread of the block
+// must reach the barrier.
+constexpr int kMatMax = 256;
+struct LdsMat {
+  double er[kMatMax], sg[kMatMax], tcr[kMatMax];
+};
+__device__ __forceinline__ void lds_mat_load(const DevGrid &g, LdsMat &M) {
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x, nt = blockDim.x * blockDim.y;
+  for (int m = tid; m < g.n_mat; m += nt) {
+    const double *row = g.mtab + m * kMatStride;
+    const bool tf = row[MC_TCR] != 0.0 && row[MC_SIGS] != 0.0;
+    M.er[m] = row[MC_EPSR];
+    M.sg[m] = tf ? -row[MC_SIGS] : row[MC_SIGS];
+    M.tcr[m] = row[MC_TCR];
+  }
+  __syncthreads();
+}
+// The 8 cells around a node by id (index ox + 2 oy + 4 oz), values from LDS;
+// the same CellV as GCell gives for the same ids.
+struct LCell {
+  const LdsMat *M;
+  int id[8];
+  __device__ __forceinline__ CellV operator()(int ox, int oy, int oz) const {
+    const int m = id[ox + 2 * oy + 4 * oz];
+    const double sg = M->sg[m];
+    CellV v;
+    v.er = M->er[m];
+    v.sg = fabs(sg);
+    v.tf = sg < 0.0 ? 1 : 0;
+    v.m = m;
+    return v;
+  }
+};
+struct LTcr {
+  const LdsMat *M;
+  __device__ __forceinline__ double operator()(int m) const { return M->tcr[m]; }
+};
+
 __device__ __forceinline__ int find_port(const DevPorts &P, int64_t key) {
   int lo = 0, hi = P.n_edges - 1;
   while (lo <= hi) {
@@ -887,27 +927,40 @@ __device__ __forceinline__ double pending_joule(const DevGrid &g, const T *const
 
 // Per-node coefficients of the own x, y, z edges: eps_r and the normalised
 // material conductance a = dt sigma(T) / (2 eps0), formed in FP64 from the
-// cells around the node and stored at the field precision.
+// cells around the node (their ids read once, the material table in LDS) and
+// stored at the field precision.  An edge that does not exist keeps eps_r =
+// 1 and a = 0 and reads no temperature.
 template <typename T>
 __global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const T *th, T *cf, CoefK ck) {
+  __shared__ LdsMat MT;
+  lds_mat_load(g, MT);
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i > g.nx || j > g.ny) return;
   const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
   const double ax[2] = {g.al[0][i], g.ah[0][i]}, ay[2] = {g.al[1][j], g.ah[1][j]}, az[2] = {g.al[2][k], g.ah[2][k]};
-  GCell CL{g.mat, g.mtab, n, g.sy, g.sz, i, j, k, g.nx, g.ny, g.nz};
-  GTcr TC{g.mtab};
+  LCell CL;
+  CL.M = &MT;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int ox = q & 1, oy = (q >> 1) & 1, oz = q >> 2;
+    const int ci = i - 1 + ox, cj = j - 1 + oy, ck2 = k - 1 + oz;
+    const bool ok = ci >= 0 && ci < g.nx && cj >= 0 && cj < g.ny && ck2 >= 0 && ck2 < g.nz;
+    CL.id[q] = ok ? int(g.mat[n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz]) : 0;
+  }
+  const LTcr TC{&MT};
   GTh<T> TH{th, n, g.sy, g.sz};
-  double er[3], a[3];
-  a[0] = edge_coef<0>(1, ax, ay, az, CL, TC, TH, &er[0]);
-  a[1] = edge_coef<1>(1, ax, ay, az, CL, TC, TH, &er[1]);
-  a[2] = edge_coef<2>(1, ax, ay, az, CL, TC, TH, &er[2]);
+  const bool ex[3] = {i < g.nx, j < g.ny, k < g.nz};
+  double er[3] = {1.0, 1.0, 1.0}, a[3] = {0.0, 0.0, 0.0};
+  if (ex[0]) a[0] = edge_coef<0>(1, ax, ay, az, CL, TC, TH, &er[0]);
+  if (ex[1]) a[1] = edge_coef<1>(1, ax, ay, az, CL, TC, TH, &er[1]);
+  if (ex[2]) a[2] = edge_coef<2>(1, ax, ay, az, CL, TC, TH, &er[2]);
   const uint32_t cs = g.cs;
   const uint8_t fl = g.flags[n];
   for (int d = 0; d < 3; ++d) {
-    const double e = er[d] > 0.0 ? er[d] : 1.0;  // a missing edge keeps a harmless 1
+    const double e = er[d] > 0.0 ? er[d] : 1.0;  // an edge without cells keeps a harmless 1
     if (sizeof(T) == 4) {
       const float a2 = float(2.0 * a[d]);
-      if (ck.K) {
+      if (ck.K && ex[d]) {
         // leapfrog form: a changed from a_old to a between e_prev = e^{n-1}
         // and e_cur = e^n; K += (a - a_old) (e^n + e^{n-1})
         const float a2o = float(cf[(3 + d) * cs + n]);
@@ -936,20 +989,41 @@ __global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const 
 // C_n V_n = sum over the node's cell octants of rho_cp * octant volume.
 // The pending Joule power of the block's last EM step is added first, with
 // the conductivity of the temperature the block ran at.
-__device__ __forceinline__ void thermal_node(const ThermalLaunch &L, int i, int j, int k, int64_t n, double ps,
-                                             double &e_part, double &m_part) {
+// The thermal constants (k, rho c_p) of every material in LDS.
+struct LdsTherm {
+  double k[kMatMax], rc[kMatMax];
+};
+__device__ __forceinline__ void lds_therm_load(const DevGrid &g, LdsTherm &M) {
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x, nt = blockDim.x * blockDim.y;
+  for (int m = tid; m < g.n_mat; m += nt) {
+    M.k[m] = g.mtab[m * kMatStride + MC_K];
+    M.rc[m] = g.mtab[m * kMatStride + MC_RHOCP];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void thermal_node(const ThermalLaunch &L, const LdsTherm &M, int i, int j, int k,
+                                             int64_t n, double ps, double &e_part, double &m_part) {
   const DevGrid &g = L.g;
   const double t0 = L.theta_in[n];
-  double CV = 0.0, gx0 = 0, gx1 = 0, gy0 = 0, gy1 = 0, gz0 = 0, gz1 = 0;
+  int id[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
     const int ii = i - 1 + ox, jj = j - 1 + oy, kk = k - 1 + oz;
-    if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny || kk < 0 || kk >= g.nz) continue;
-    const double *row = g.mtab + g.mat[n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz] * kMatStride;
-    const double ddx = g.dx[ii], ddy = g.dy[jj], ddz = g.dz[kk], kc = row[MC_K];
-    CV += row[MC_RHOCP] * 0.125 * ddx * ddy * ddz;
-    const double wx = 0.25 * ddy * ddz * kc / ddx, wy = 0.25 * ddx * ddz * kc / ddy, wz = 0.25 * ddx * ddy * kc / ddz;
+    const bool ok = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
+    id[c] = ok ? int(g.mat[n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz]) : -1;
+  }
+  double CV = 0.0, gx0 = 0, gx1 = 0, gy0 = 0, gy1 = 0, gz0 = 0, gz1 = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (id[c] < 0) continue;
+    const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+    const int ii = i - 1 + ox, jj = j - 1 + oy, kk = k - 1 + oz;
+    const double ddx = g.dx[ii], ddy = g.dy[jj], ddz = g.dz[kk], kc = M.k[id[c]];
+    CV += M.rc[id[c]] * 0.125 * ddx * ddy * ddz;
+    const double wx = 0.25 * ddy * ddz * kc * g.idx[ii], wy = 0.25 * ddx * ddz * kc * g.idy[jj],
+                 wz = 0.25 * ddx * ddy * kc * g.idz[kk];
     if (ox) gx1 += wx; else gx0 += wx;
     if (oy) gy1 += wy; else gy0 += wy;
     if (oz) gz1 += wz; else gz0 += wz;
@@ -970,9 +1044,12 @@ __device__ __forceinline__ void thermal_node(const ThermalLaunch &L, int i, int 
   m_part = tn;
 }
 
+// One thread per node, one block per 64 x 4 node tile of a plane.
 template <typename T>
 __global__ __launch_bounds__(256) void thermal_kernel(ThermalLaunch L, const T *e0, const T *e1, const T *e2,
                                                       const T *cf) {
+  __shared__ LdsTherm MT;
+  lds_therm_load(L.g, MT);
   const DevGrid &g = L.g;
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   double e_part = 0.0, m_part = -1.0e300;
@@ -984,9 +1061,9 @@ __global__ __launch_bounds__(256) void thermal_kernel(ThermalLaunch L, const T *
       const double P = pending_joule<T>(g, e, cf, i, j, k, n, L.jf);
       if (P != 0.0) ps += P;
     }
-    thermal_node(L, i, j, k, n, ps, e_part, m_part);
-    // the max reduction (fmax) drops NaN: carry a non-finite temperature in
-    // the energy sum, which the finalize kernel checks
+    thermal_node(L, MT, i, j, k, n, ps, e_part, m_part);
+    // the max reduction (fmax) drops NaN: carry a non-finite temperature
+    // in the energy sum, which the finalize kernel checks
     if (!isfinite(m_part)) e_part = m_part - m_part;
   }
   const double s[1] = {e_part}, m[1] = {m_part};
@@ -1024,6 +1101,17 @@ __device__ void reduce_partials(const double *part, int64_t nb, int n_sum, int n
       for (int w = 1; w < (int)(blockDim.x / 64); ++w) acc = q < n_sum ? acc + red[w][q] : fmax(acc, red[w][q]);
       out[q] = acc;
     }
+}
+
+// First stage of a two-stage reduction: block b folds rows [b per, (b+1) per)
+// of the partials, in a fixed order, into row b of out.
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const double *part, int64_t nb, int64_t per, int n_sum,
+                                                          int n_max, double *out) {
+  __shared__ double o[kRedWidth];
+  const int64_t b0 = int64_t(blockIdx.x) * per, b1 = b0 + per < nb ? b0 + per : nb;
+  reduce_partials(part + b0 * kRedWidth, b1 > b0 ? b1 - b0 : 0, n_sum, n_max, o);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < n_sum + n_max; ++q) out[int64_t(blockIdx.x) * kRedWidth + q] = o[q];
 }
 
 __global__ __launch_bounds__(256) void thermal_finalize(const double *part, int64_t nb, DevScalars *sc) {
@@ -1259,7 +1347,16 @@ hipError_t launch_thermal(const ThermalLaunch &L, hipStream_t s) {
     hipLaunchKernelGGL((thermal_kernel<float>), grid, block, 0, s, L, (const float *)L.e[0], (const float *)L.e[1],
                        (const float *)L.e[2], (const float *)L.coef);
   const int64_t nb = int64_t(grid.x) * grid.y * grid.z;
-  hipLaunchKernelGGL(thermal_finalize, dim3(1), dim3(256), 0, s, (const double *)L.partials, nb, L.sc);
+  if (nb > 4 * kFinalizeRows) {
+    // two stages: rows [nb, nb + kFinalizeRows) of the partials hold the first
+    const int64_t per = (nb + kFinalizeRows - 1) / kFinalizeRows, nb2 = (nb + per - 1) / per;
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(unsigned(nb2)), dim3(256), 0, s, (const double *)L.partials, nb, per,
+                       1, 1, L.partials + nb * kRedWidth);
+    hipLaunchKernelGGL(thermal_finalize, dim3(1), dim3(256), 0, s, (const double *)(L.partials + nb * kRedWidth),
+                       nb2, L.sc);
+  } else {
+    hipLaunchKernelGGL(thermal_finalize, dim3(1), dim3(256), 0, s, (const double *)L.partials, nb, L.sc);
+  }
   return hipGetLastError();
 }
 

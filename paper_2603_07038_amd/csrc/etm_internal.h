@@ -109,6 +109,9 @@ enum { kSolveRunning = 0, kSolveConverged = 1, kSolveGaveUp = 3 };
 
 // Reduction partials: per block, up to 4 doubles.
 constexpr int kRedWidth = 4;
+// Rows after a kernel's own partials that a two-stage reduction uses for its
+// first stage.
+constexpr int64_t kFinalizeRows = 512;
 
 // ---- launchers (kernels in em.hip, mech.hip) ------------------------------
 struct EmLaunch {

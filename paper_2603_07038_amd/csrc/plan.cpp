@@ -447,7 +447,7 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   take(p->r_theta[0], N * 8);
   take(p->r_theta[1], N * 8);
   take(p->r_psum, N * 8);
-  take(p->r_part, size_t(std::max<int64_t>(p->nblocks_node, 1024)) * kRedWidth * 8);
+  take(p->r_part, size_t(std::max<int64_t>(p->nblocks_node, 1024) + kFinalizeRows) * kRedWidth * 8);
   take(p->r_sc, sizeof(DevScalars));
   // the mechanical solve owns its partials, scalars and temperature copy, so
   // that it can run beside the march on another stream
