@@ -43,7 +43,9 @@ Further legs (on by default; --legs selects):
   batch      64 design variants of uneven size, one batched mixed run against
              64 sequential FP64 runs and a batched FP64 run;
   serve      Poisson arrivals through the continuous-batching server, mixed
-             and FP64 (--serve-rates, --serve-requests);
+             and FP64 (--serve-rates, --serve-requests, --serve-precisions;
+             --serve-only runs this leg alone, e.g. the sweep of 256 requests
+             at 2, 5, 10 and 20 req/s);
   cpu        the FP64 oracle on the host cores: a bounded window of the
              package (one EM step, Joule and a thermal step), a sample of the
              slice with its thermal step, the full 32x32x16 trace case, and
@@ -89,6 +91,9 @@ def parse():
     ap.add_argument("--batch-variants", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-rates", default="2")
+    ap.add_argument("--serve-precisions", default="mixed,fp64")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg (a rate sweep) and print its JSON line")
     ap.add_argument("--probe", choices=["em", "em-fp64", "em-slice", "em-slice-fp64", "mech", "copy", "r1", "r1-fp64"],
                     default=None,
                     help="short runs for hardware-counter profiles: 8 EM steps of the package (em, em-fp64) or the "
@@ -483,31 +488,56 @@ def batch_leg(n_variants):
     return res
 
 
-def serve_leg(n_requests, rates):
-    """Continuous-batching server under Poisson arrivals, mixed and FP64."""
+def serve_leg(n_requests, rates, precisions=("mixed", "fp64")):
+    """Continuous-batching server under Poisson arrivals, mixed and FP64.
+
+    Per rate and precision: latency percentiles, designs/hour and the
+    sustained fraction (answered requests per second over the offered rate).
+    The knee is the highest rate whose p99 latency stays within twice the p99
+    at the lowest rate while at least 90% of the offered rate is sustained."""
     import torch
     import workloads as W
     import paper_2603_07038_amd as etm
     from paper_2603_07038_amd import serve
     probs = [W.config5_request(r) for r in range(n_requests)]
     res = {"requests_per_rate": n_requests, "mean_cells": round(sum(p.n_cells for p in probs) / n_requests),
+           "mean_em_steps": round(sum(p.n_em_steps for p in probs) / n_requests),
            "arrivals": "Poisson, seed 5999", "rates": {}}
+    precs = {"mixed": etm.ETM_PREC_MIXED, "fp64": etm.ETM_PREC_FP64}
     for rate in rates:
         arrivals = W.poisson_arrivals(rate, n_requests)
         one = {}
-        for name, prec in (("mixed", etm.ETM_PREC_MIXED), ("fp64", etm.ETM_PREC_FP64)):
+        for name in precisions:
             reqs = [serve.Request(p, float(t), r) for r, (p, t) in enumerate(zip(probs, arrivals))]
-            srv = serve.Server(max_slots=16, hbm_budget=96e9, precision=prec)
+            srv = serve.Server(max_slots=16, hbm_budget=96e9, precision=precs[name])
             torch.cuda.synchronize()
             t = time.perf_counter()
-            done = srv.run(reqs, realtime=True)
+
+            last = [0]
+
+            def progress(done, t=t, name=name, last=last):
+                if len(done) // 32 > last[0] or len(done) == n_requests:
+                    last[0] = len(done) // 32
+                    say(f"[serve] {name} {rate} req/s: {len(done)}/{n_requests} answered at "
+                        f"{time.perf_counter() - t:.1f} s")
+            done = srv.run(reqs, realtime=True, progress=progress)
             wall = time.perf_counter() - t
             summ = serve.summarize(done, wall)
+            summ["sustained_frac"] = summ["completed"] / wall / rate if wall > 0 else None
             one[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
             del srv
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
         res["rates"][str(rate)] = one
+    for name in precisions:
+        pts = [(float(r), v[name]) for r, v in res["rates"].items() if name in v]
+        pts.sort()
+        if not pts:
+            continue
+        p99_0 = pts[0][1]["p99_s"]
+        ok = [r for r, v in pts if v["p99_s"] <= 2.0 * p99_0 and (v["sustained_frac"] or 0.0) >= 0.9]
+        res[f"knee_{name}_req_per_s"] = max(ok) if ok else None
+    res["knee_rule"] = "highest rate with p99 <= 2x the p99 at the lowest rate and >= 90% of the offered rate answered"
     return res
 
 
@@ -583,6 +613,10 @@ def main():
     import paper_2603_07038_amd as etm
     etm.load()
     torch.cuda.init()
+    serve_args = (a.serve_requests, [float(r) for r in a.serve_rates.split(",")], a.serve_precisions.split(","))
+    if a.serve_only:
+        print(json.dumps({"serving": serve_leg(*serve_args)}))
+        return
     legs = set(a.legs.split(","))
     prob, dt, mixed, fp64, cmp = headline(a.steps, a.warmup)
     extra = {"copy_ceiling": copy_ceiling()}
@@ -597,7 +631,7 @@ def main():
         extra["batch"] = batch_leg(a.batch_variants)
     if "serve" in legs:
         say("[bench] leg serve")
-        extra["serving"] = serve_leg(a.serve_requests, [float(r) for r in a.serve_rates.split(",")])
+        extra["serving"] = serve_leg(*serve_args)
     cpu = None
     if "cpu" in legs and not a.no_cpu:
         say("[bench] leg cpu")

@@ -159,15 +159,21 @@ class Server:
                 plan.ws = None
         self.solving = keep
 
-    def run(self, requests: List[Request], realtime: bool = True) -> List[Result]:
+    def run(self, requests: List[Request], realtime: bool = True, progress=None) -> List[Result]:
         """Serve all requests; arrivals are honoured in wall-clock time when
-        ``realtime`` (else every request is available at once)."""
+        ``realtime`` (else every request is available at once).  ``progress``,
+        if given, is called with the list of answered requests each time it
+        has grown."""
         pending = sorted(requests, key=lambda r: r.arrival)
         queue: List = []
         done: List[Result] = []
         self._t0 = t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
+        n_seen = 0
         while pending or queue or self.active or self.solving:
+            if progress is not None and len(done) != n_seen:
+                n_seen = len(done)
+                progress(done)
             t = now()
             while pending and (not realtime or pending[0].arrival <= t):
                 r = pending.pop(0)
