@@ -282,7 +282,7 @@ def headline(steps, warmup):
 
 
 # ---- the slice with a mechanical solve after every thermal step -----------------
-def slice_leg(steps=3, warmup=1):
+def slice_leg(steps=3, warmup=1, tail_blocks=5):
     import torch
     import workloads as W
     import paper_2603_07038_amd as etm
@@ -301,7 +301,7 @@ def slice_leg(steps=3, warmup=1):
         # blocks in parts: the march (R - 1 steps) and the tail (last EM step,
         # thermal step, mechanical solve and von Mises; a solve that ends an
         # advance call runs without overlap)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2)]
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(tail_blocks)]
         tail_ms = 0.0
         for e in ev:
             e[0].record(stream)
@@ -326,9 +326,10 @@ def slice_leg(steps=3, warmup=1):
         _, _, dofs = plan.dofs()
         out[name] = {"coupled_with_mechanics_mcell_steps_per_s": round(prob.n_cells * R * steps / wall / 1e6, 1),
                      "ms_per_block": round(wall / steps * 1e3, 2),
-                     "march_mcell_steps_per_s": round(prob.n_cells * (R - 1) * 2 / (em_ms / 1e3) / 1e6, 1),
-                     "em_kernel_us": round(em_ms * 1e3 / (2 * (R - 1)), 2),
-                     "mech_tail_ms_per_block": round(tail_ms / 2, 2), "cg_iters_per_block": split_iters / 2,
+                     "march_mcell_steps_per_s": round(prob.n_cells * (R - 1) * tail_blocks / (em_ms / 1e3) / 1e6, 1),
+                     "em_kernel_us": round(em_ms * 1e3 / (tail_blocks * (R - 1)), 2),
+                     "mech_tail_ms_per_block": round(tail_ms / tail_blocks, 2),
+                     "cg_iters_per_block": split_iters / tail_blocks,
                      "cg_dof_iter_per_s": dofs * split_iters / (tail_ms / 1e3) if split_iters else None}
         del plan
         torch.cuda.synchronize()

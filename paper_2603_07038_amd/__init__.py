@@ -217,6 +217,8 @@ def make_opts(prob, *, dt=0.0, precision=ETM_PREC_FP64, n_steps=None, mech_mask=
         o.probes = pr.ctypes.data_as(C.POINTER(C.c_int64))
     o.n_em_steps_hint = int(prob.n_em_steps if n_steps is None else n_steps)
     for k, v in overrides.items():
+        if isinstance(v, (list, tuple)):   # array fields (em_bc, mg_degree)
+            v = type(getattr(o, k))(*v)
         setattr(o, k, v)
     return o, keep
 

@@ -150,10 +150,14 @@ __device__ __forceinline__ void hex8_cell(T ux[8], T uy[8], T uz[8], T hx, T hy,
 // cell's K_e and stores the 24 results in LDS, and each owned node adds the
 // corners of its four cells in a fixed order, so y is deterministic.
 // Fixed DOFs give zero rows; x is taken as zero on them.  The next x plane
-// and the epilogue's own inputs (Epi::load, issued before the cell work)
-// are fetched one layer ahead.  The epilogue sees (n, y, x at the node, its
-// prefetched inputs, per-thread partial sums).
+// and the material id of the cell below it are fetched one layer ahead; the
+// Lame constants come from a per-block LDS copy of the material table (mu
+// stored as -1 for a void material), so no global load sits between the
+// barrier and the cell work.  The epilogue's own inputs (Epi::load) and the
+// node's fixed-DOF bits are issued before the cell work.  The epilogue sees
+// (n, y, x at the node, its prefetched inputs, per-thread partial sums).
 constexpr int CX = 32, CY = 8;
+constexpr int kMatMaxMech = 256;  // material ids are 8-bit
 
 inline dim3 cell_grid(const DevGrid &g, int kchunk) {
   return dim3((g.nx + 1 + CX - 2) / (CX - 1), (g.ny + 1 + CY - 2) / (CY - 1), (g.nz + 1 + kchunk - 1) / kchunk);
@@ -174,7 +178,13 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
   constexpr int PT = (PL + CX * CY - 1) / (CX * CY);  // plane entries per thread
   __shared__ T xs[3][3][CY + 1][CX + 1];
   __shared__ T co[24][CY][CX];
+  __shared__ T lm_tab[2][kMatMaxMech];
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * CX + tx;
+  for (int m = tid; m < g.n_mat; m += CX * CY) {
+    const double *row = g.mtab + m * kMatStride;
+    lm_tab[0][m] = T(row[MC_LAMBDA]);
+    lm_tab[1][m] = row[MC_VOID] == 0.0 ? T(row[MC_MU]) : T(-1);
+  }
   // logical tile of this block: XCD-contiguous, x fastest, so tiles that
   // share cache lines at their x and y borders share an L2
   const int nbx = int(gridDim.x), nby = int(gridDim.y);
@@ -193,7 +203,10 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
   for (int q = 0; q < (NS > 0 ? NS : 1); ++q) red[q] = 0.0;
   // plane k of x into registers (this thread's share), then into LDS
   T pf[PT][3];
+  int pm = -1, mid = -1;  // material id of cell (ci, cj, k - 1): fetched with plane k
   auto fetch = [&](int k) {
+    const bool cl = cin && k >= 1 && k <= g.nz;
+    pm = cl ? int(g.mat[int64_t(k - 1) * g.sz + int64_t(cj) * g.sy + ci]) : -1;
 #pragma unroll
     for (int e = 0; e < PT; ++e) {
       const int t = tid + e * CX * CY;
@@ -206,6 +219,7 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
     }
   };
   auto stage = [&](int k) {
+    mid = pm;
     T(*dst)[CY + 1][CX + 1] = xs[(k + 3) % 3];
 #pragma unroll
     for (int e = 0; e < PT; ++e) {
@@ -227,18 +241,21 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
     const int64_t n = int64_t(ck) * g.sz + int64_t(nj) * g.sy + ni;
     const bool emit = own && ck >= k0;
     typename Epi::Pre pre;
-    if (emit) pre = epi.load(n);
+    uint8_t fix = 0;
+    if (emit) {
+      pre = epi.load(n);
+      fix = M.fixed[n];
+    }
+    const int m = mid;    // cell layer ck (staged with plane ck + 1)
+    const T hz = m >= 0 ? T(g.dz[ck]) : T(1);
     __syncthreads();
     T ux[8], uy[8], uz[8];
-    bool live = cin && ck >= 0 && ck < g.nz;
-    T lam = T(0), mu = T(0), hz = T(1);
-    if (live) {
-      const double *row = g.mtab + g.mat[int64_t(ck) * g.sz + int64_t(cj) * g.sy + ci] * kMatStride;
-      live = row[MC_VOID] == 0.0;
-      lam = T(row[MC_LAMBDA]);
-      mu = T(row[MC_MU]);
-      hz = T(g.dz[ck]);
+    T lam = T(0), mu = T(-1);
+    if (m >= 0) {
+      lam = lm_tab[0][m];
+      mu = lm_tab[1][m];
     }
+    const bool live = mu >= T(0);
     if (live) {
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
@@ -272,10 +289,9 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
                  co[4 * 3 + q][ty + 1][tx + 1];
       }
       if (emit) {
-        const uint8_t f = M.fixed[n];
-        if (f & 1) y[0] = T(0);
-        if (f & 2) y[1] = T(0);
-        if (f & 4) y[2] = T(0);
+        if (fix & 1) y[0] = T(0);
+        if (fix & 2) y[1] = T(0);
+        if (fix & 4) y[2] = T(0);
         const T(*pl)[CY + 1][CX + 1] = xs[(ck + 3) % 3];
         const T xc[3] = {pl[0][ty + 1][tx + 1], pl[1][ty + 1][tx + 1], pl[2][ty + 1][tx + 1]};
         epi(n, y, xc, pre, red);

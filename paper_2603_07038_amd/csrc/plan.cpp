@@ -1089,6 +1089,7 @@ etm_status mech_solve_impl(etm_plan *p) {
   }
   if ((st = enqueue_passes_any(p, n_pass, iters)) != ETM_OK) return st;
   p->solve_enqueued = 0;
+  p->solve_rounds = 0;
   for (int q = 0; q < n_pass; ++q) p->solve_enqueued += iters[q];
   p->solve_pending = true;
   p->n_solves++;
@@ -1105,18 +1106,20 @@ etm_status solve_settle(etm_plan *p) {
     HIP_TRY(hipEventSynchronize(p->ev_solve));
     const DevScalars c = *p->ctl_host;
     if (c.done == kSolveRunning) {
-      // more passes, on the plan's stream after what was enqueued: as many
-      // iterations again as so far (at least 32), so that a long solve needs
-      // few of these round trips
+      // one more pass, on the plan's stream after what was enqueued.  Its
+      // length grows with the round trips already taken (8, 16, 32, ...
+      // iterations up to the work enqueued so far): a solve that is just
+      // short of its plan pays few skipped iterations, a long one few round
+      // trips.
       HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_solve, 0));
-      const int add = std::max(32, p->solve_enqueued);
-      const int more[2] = {add / 2, add - add / 2};
-      etm_status st = enqueue_passes_any(p, 2, more);
+      const int add = std::min(std::max(8, p->solve_enqueued), 8 << std::min(p->solve_rounds, 8));
+      etm_status st = enqueue_passes_any(p, 1, &add);
       if (st != ETM_OK) {
         p->solve_pending = false;
         return st;
       }
       p->solve_enqueued += add;
+      p->solve_rounds += 1;
       continue;
     }
     p->solve_pending = false;
@@ -1124,11 +1127,14 @@ etm_status solve_settle(etm_plan *p) {
     p->cg_outer = c.outer;
     p->cg_total += c.iters;
     p->cg_relres = c.fnorm2 > 0 ? std::sqrt(c.rr / c.fnorm2) : 0.0;
-    // the next solve's passes: each a little longer than this solve's
+    // the next solve's passes: each one iteration (and 1/16) longer than
+    // this solve's.  An iteration enqueued but not needed still launches its
+    // kernels, which exit at once (about 0.3 ms per iteration on a 4M-node
+    // mesh); one missing ends the pass early and costs a restart.
     int n = 0;
     for (int q = 0; q + 1 < c.outer && q < kMaxPasses; ++q) {
       if (c.pass_iters[q] <= 0) break;
-      p->pass_plan[n++] = c.pass_iters[q] + c.pass_iters[q] / 4 + 2;
+      p->pass_plan[n++] = c.pass_iters[q] + c.pass_iters[q] / 16 + 1;
     }
     if (c.done == kSolveConverged && n > 0) p->pass_plan_n = n;
     if (c.done != kSolveConverged && p->host_status == ETM_OK) {

@@ -102,6 +102,7 @@ struct etm_plan {
   DevScalars *ctl_host = nullptr;  // pinned copy of the solve's control block (written by the device)
   bool solve_pending = false;      // a solve is enqueued and not yet settled
   int solve_enqueued = 0;          // inner iterations enqueued for it so far
+  int solve_rounds = 0;            // passes added to it at settle
   int pass_plan_n = 0;             // passes to enqueue for the next solve (0: no history yet)
   int pass_plan[kMaxPasses] = {};  // inner iterations of each
   int64_t step = 0;
