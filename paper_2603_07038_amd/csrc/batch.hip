@@ -229,6 +229,7 @@ etm_status run_segment(etm_batch *b, int len, hipStream_t st, const BatchDev &D)
 // step or a history record, then that host-side work per variant.  `D` says
 // where the kernels find their descriptors, work list and counter.
 etm_status advance_impl(etm_batch *b, int64_t n, hipStream_t caller, const BatchDev &D) {
+  Range r_call("etm_batch_advance");
   hipStream_t st = b->run;
   const size_t nv = b->order.size();
   // the batch stream runs after the caller's stream and after each plan's own stream

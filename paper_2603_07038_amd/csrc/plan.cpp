@@ -1032,6 +1032,7 @@ etm_status enqueue_passes_any(etm_plan *p, int n_pass, const int *iters) {
 etm_status mech_solve_impl(etm_plan *p) {
   etm_status st;
   if ((st = solve_settle(p)) != ETM_OK) return st;  // the previous solve owns u and the scalars
+  Range r("etm:mech_solve_enqueue");
   const MechGrid M = p->mech_grid();
   const int64_t N = p->ntot;
   double *u64[3], *f64[3], *r64[3], *dinv64[3];
@@ -1102,6 +1103,7 @@ etm_status mech_solve_impl(etm_plan *p) {
 // sets ETM_E_NOCONV, reported by etm_sync; only HIP errors are returned.
 etm_status solve_settle(etm_plan *p) {
   if (!p->solve_pending) return ETM_OK;
+  Range r("etm:mech_solve_settle");
   for (;;) {
     HIP_TRY(hipEventSynchronize(p->ev_solve));
     const DevScalars c = *p->ctl_host;
@@ -1282,6 +1284,7 @@ etm_status etm_advance(etm_plan *p, int64_t n) {
   if (!p) return fail(ETM_E_INVAL, "null plan");
   if (!p->bound) return fail(ETM_E_STATE, "plan is not bound");
   if (n < 0) return fail(ETM_E_INVAL, "negative step count");
+  Range r_call("etm_advance");
   etm_status st;
   const int64_t hs = p->opts.history_stride;
   auto history_due = [&](int64_t s) { return hs > 0 && s % hs == 0; };
@@ -1289,6 +1292,7 @@ etm_status etm_advance(etm_plan *p, int64_t n) {
   // One EM step, or a pair when enabled, at most `limit` steps, and nothing
   // is due after the first of the two.
   auto march = [&](int64_t limit) -> etm_status {
+    Range r("etm:em_step");
     const bool pair = p->opts.em_slabs >= 2 && limit >= 2 && (p->step + 1) % p->R != 0 && !history_due(p->step + 1);
     const etm_status s2 = pair ? em_two_steps(p) : em_one_step(p);
     if (s2 == ETM_OK) q += pair ? 2 : 1;
@@ -1299,7 +1303,10 @@ etm_status etm_advance(etm_plan *p, int64_t n) {
     const int old = previous_state(p);
     bool hist = history_due(p->step);
     if (p->step % p->R == 0) {
-      if ((st = thermal_one(p)) != ETM_OK) return st;
+      {
+        Range r("etm:thermal_step");
+        if ((st = thermal_one(p)) != ETM_OK) return st;
+      }
       if (p->opts.mech_every_thermal > 0 && p->n_thermal % p->opts.mech_every_thermal == 0) {
         if (p->opts.mech_overlap) {
           // The record of this step first (it does not read the mechanics,

@@ -1,11 +1,24 @@
 // Private host-side plan of the library (shared by plan.cpp and batch.hip).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <string>
 #include <vector>
 
 #include "etm_internal.h"
+
+namespace etm {
+// A host-side roctx range over a scope (the enqueue of a phase, or a wait):
+// EM steps, thermal step, mechanical solve, settle, batch advance.  Seen by
+// rocprofv3 --marker-trace; a call without a tool attached does nothing.
+struct Range {
+  explicit Range(const char *name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
+}  // namespace etm
 
 namespace etm {
 etm_status fail(etm_status s, const std::string &msg);

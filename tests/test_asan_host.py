@@ -38,7 +38,8 @@ def test_host_paths_clean_under_asan(tmp_path):
     with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
         objs = list(ex.map(compile_one, SOURCES + ["asan_host_paths.cpp"]))
     exe = str(tmp_path / "asan_host_paths")
-    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=address", "-o", exe] + objs,
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=address", "-o", exe] + objs
+                       + ["-lrocprofiler-sdk-roctx"],
                        capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-4000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1:exitcode=99")
