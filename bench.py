@@ -94,10 +94,11 @@ def parse():
     ap.add_argument("--serve-precisions", default="mixed,fp64")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving leg (a rate sweep) and print its JSON line")
-    ap.add_argument("--probe", choices=["em", "em-fp64", "em-slice", "em-slice-fp64", "mech", "copy", "r1", "r1-fp64"],
+    ap.add_argument("--probe", choices=["em", "em-fp64", "em-slice", "em-slice-fp64", "em-slice-pairs3",
+                                        "em-slice-pairs8", "mech", "copy", "r1", "r1-fp64"],
                     default=None,
                     help="short runs for hardware-counter profiles: 8 EM steps of the package (em, em-fp64) or the "
-                         "slice (em-slice*), 8 coupled steps of the package at R = 1 (r1, r1-fp64), two slice "
+                         "slice (em-slice, em-slice-fp64; em-slice-pairsS: as 4 slab pairs over S z-slabs), 8 coupled steps of the package at R = 1 (r1, r1-fp64), two slice "
                          "coupling blocks with their mechanical solves (mech), or a plain 2 GiB device copy (the "
                          "calibration kernel for FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
@@ -139,7 +140,8 @@ def probe(kind):
     dt = etm.cfl_dt(prob)
     J = prob.sample_J_half(dt, 16)
     prec = etm.ETM_PREC_FP64 if kind.endswith("fp64") else etm.ETM_PREC_MIXED
-    plan = etm.Plan(prob, J, dt=dt, precision=prec, n_steps=16, history=False)
+    slabs = int(kind[len("em-slice-pairs"):]) if kind.startswith("em-slice-pairs") else 0
+    plan = etm.Plan(prob, J, dt=dt, precision=prec, n_steps=16, history=False, em_slabs=slabs)
     plan.advance(8)
     plan.sync()
     print(json.dumps({"probe": kind, "workload": prob.name, "cells": prob.n_cells, "em_steps": 8}))
