@@ -95,10 +95,11 @@ def parse():
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving leg (a rate sweep) and print its JSON line")
     ap.add_argument("--probe", choices=["em", "em-fp64", "em-slice", "em-slice-fp64", "em-slice-pairs3",
-                                        "em-slice-pairs8", "mech", "copy", "r1", "r1-fp64"],
+                                        "em-slice-pairs8", "mech", "mech-tail", "copy", "r1", "r1-fp64"],
                     default=None,
                     help="short runs for hardware-counter profiles: 8 EM steps of the package (em, em-fp64) or the "
-                         "slice (em-slice, em-slice-fp64; em-slice-pairsS: as 4 slab pairs over S z-slabs), 8 coupled steps of the package at R = 1 (r1, r1-fp64), two slice "
+                         "slice (em-slice, em-slice-fp64; em-slice-pairsS: as 4 slab pairs over S z-slabs), the "
+                         "slice's serial block tail after 6 warm blocks, 3 times (mech-tail), 8 coupled steps of the package at R = 1 (r1, r1-fp64), two slice "
                          "coupling blocks with their mechanical solves (mech), or a plain 2 GiB device copy (the "
                          "calibration kernel for FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
@@ -122,6 +123,25 @@ def probe(kind):
         return
     import workloads as W
     import paper_2603_07038_amd as etm
+    if kind == "mech-tail":
+        prob = W.config2()
+        dt = etm.cfl_dt(prob)
+        R = prob.em_per_thermal
+        J = prob.sample_J_half(dt, prob.n_em_steps)
+        plan = etm.Plan(prob, J, dt=dt, precision=etm.ETM_PREC_MIXED, n_steps=prob.n_em_steps, history=False)
+        plan.advance(6 * R)
+        plan.sync()
+        tails = []
+        for _ in range(3):
+            plan.advance(R - 1)
+            plan.sync()
+            t = time.perf_counter()
+            plan.advance(1)      # last EM step, thermal step, solve, von Mises
+            info = plan.sync()
+            tails.append({"ms": round((time.perf_counter() - t) * 1e3, 2), "cg_iters": info["cg_iters"],
+                          "cg_outer": info["cg_outer"]})
+        print(json.dumps({"probe": kind, "workload": prob.name, "cells": prob.n_cells, "tails": tails}))
+        return
     if kind == "mech":
         prob = W.config2()
         dt = etm.cfl_dt(prob)
@@ -535,7 +555,7 @@ def serve_leg(n_requests, rates, precisions=("mixed", "fp64")):
     for name in precisions:
         pts = [(float(r), v[name]) for r, v in res["rates"].items() if name in v]
         pts.sort()
-        if not pts:
+        if len(pts) < 2:   # a knee needs a sweep
             continue
         p99_0 = pts[0][1]["p99_s"]
         ok = [r for r, v in pts if v["p99_s"] <= 2.0 * p99_0 and (v["sustained_frac"] or 0.0) >= 0.9]
