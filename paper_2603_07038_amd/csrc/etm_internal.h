@@ -274,8 +274,9 @@ hipError_t launch_vec_zero32(float *x, int64_t n, const DevScalars *gate, hipStr
 hipError_t launch_vec_axpy64(double *y, const float *x, int64_t n, const DevScalars *gate, hipStream_t s);  // y += x
 // u_c <- 0 at every fixed DOF c of the plan's constraints
 hipError_t launch_mask_fixed(const MechGrid &M, int c, double *u, hipStream_t s);
-// u <- u + sc (u - uprev), uprev <- previous u
-hipError_t launch_extrapolate(double *u[3], double *uprev[3], double sc, int64_t n, hipStream_t s);
+// u <- w0 u + w1 uprev + w2 uprev2, uprev2 <- uprev, uprev <- previous u
+hipError_t launch_extrapolate(double *u[3], double *uprev[3], double *uprev2[3], const double w[3], int64_t n,
+                              hipStream_t s);
 hipError_t launch_von_mises(const MechGrid &M, const double *theta, const double *u[3], double *vm,
                             hipStream_t s);
 

@@ -315,16 +315,18 @@ __global__ void mask_fixed_kernel(const uint8_t *fixed, int c, double *u, int64_
     if (fixed[t] >> c & 1) u[t] = 0.0;
 }
 
-// u <- u + s (u - u_prev), u_prev <- old u (per component arrays).
-__global__ void extrapolate_kernel(double *u0, double *u1, double *u2, double *v0, double *v1, double *v2, double sc,
-                                   int64_t n) {
+// u <- w0 u + w1 u_prev + w2 u_prev2, u_prev2 <- u_prev, u_prev <- old u.
+struct Hist3 {
+  double *u[3], *v[3], *q[3];
+};
+__global__ void extrapolate_kernel(Hist3 H, double w0, double w1, double w2, int64_t n) {
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
-    double *u[3] = {u0, u1, u2}, *v[3] = {v0, v1, v2};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double a = u[c][t], b = v[c][t];
-      u[c][t] = a + sc * (a - b);
-      v[c][t] = a;
+      const double a = H.u[c][t], b = H.v[c][t], d = H.q[c][t];
+      H.u[c][t] = w0 * a + w1 * b + w2 * d;
+      H.q[c][t] = b;
+      H.v[c][t] = a;
     }
   }
 }
@@ -486,9 +488,11 @@ hipError_t launch_vec_zero32(float *x, int64_t n, const DevScalars *gate, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_extrapolate(double *u[3], double *uprev[3], double sc, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(extrapolate_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, u[0], u[1], u[2], uprev[0], uprev[1],
-                     uprev[2], sc, n);
+hipError_t launch_extrapolate(double *u[3], double *uprev[3], double *uprev2[3], const double w[3], int64_t n,
+                              hipStream_t s) {
+  Hist3 H;
+  for (int c = 0; c < 3; ++c) { H.u[c] = u[c]; H.v[c] = uprev[c]; H.q[c] = uprev2[c]; }
+  hipLaunchKernelGGL(extrapolate_kernel, dim3(flat_blocks(n)), dim3(256), 0, s, H, w[0], w[1], w[2], n);
   return hipGetLastError();
 }
 

@@ -461,6 +461,7 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   for (int c = 0; c < 3; ++c) {
     take(p->r_u64[c], N * 8); take(p->r_f64[c], N * 8); take(p->r_r64[c], N * 8); take(p->r_dinv64[c], N * 8);
     take(p->r_uprev64[c], N * 8);
+    take(p->r_uprev2_64[c], N * 8);
   }
   if (p->prec == ETM_PREC_FP64) {
     for (int c = 0; c < 3; ++c) { take(p->r_p64[c], N * 8); take(p->r_w64[c], N * 8); }
@@ -1052,19 +1053,35 @@ etm_status mech_solve_impl(etm_plan *p) {
         HIP_TRY(launch_vec_cast(dinv64[c], 0, p->ptr<float>(p->r_dinv32[c]), 1, N, nullptr, p->stream));
     p->dinv_ready = true;
   }
-  // Initial guess: the last solution, extrapolated linearly in time through
-  // the one before it (thermal-step counts of the two solves).  Only the
-  // starting point of CG changes; convergence is still judged on the FP64
-  // residual of the new system.
-  double *uprev[3];
-  for (int c = 0; c < 3; ++c) uprev[c] = p->ptr<double>(p->r_uprev64[c]);
+  // Initial guess: the last solution, extrapolated in time through the ones
+  // before it (a Lagrange polynomial in the thermal-step counts of up to the
+  // last three solves: quadratic once three exist).  Only the starting point
+  // of CG changes; convergence is still judged on the FP64 residual of the
+  // new system.
+  double *uprev[3], *uprev2[3];
+  for (int c = 0; c < 3; ++c) {
+    uprev[c] = p->ptr<double>(p->r_uprev64[c]);
+    uprev2[c] = p->ptr<double>(p->r_uprev2_64[c]);
+  }
   const int64_t tn = p->n_thermal;
   if (p->sol_t[0] >= 0 && tn != p->sol_t[0]) {
-    const double sc = (p->sol_t[1] >= 0 && p->sol_t[0] > p->sol_t[1])
-                          ? double(tn - p->sol_t[0]) / double(p->sol_t[0] - p->sol_t[1]) : 0.0;
-    HIP_TRY(launch_extrapolate(u64, uprev, sc, N, p->stream));
+    const double x = double(tn), t0 = double(p->sol_t[0]), t1 = double(p->sol_t[1]), t2 = double(p->sol_t[2]);
+    double w[3] = {1.0, 0.0, 0.0};
+    if (p->sol_t[2] >= 0 && t2 < t1 && t1 < t0) {
+      w[0] = (x - t1) * (x - t2) / ((t0 - t1) * (t0 - t2));
+      w[1] = (x - t0) * (x - t2) / ((t1 - t0) * (t1 - t2));
+      w[2] = (x - t0) * (x - t1) / ((t2 - t0) * (t2 - t1));
+    } else if (p->sol_t[1] >= 0 && t1 < t0) {
+      w[0] = (x - t1) / (t0 - t1);
+      w[1] = (x - t0) / (t1 - t0);
+    }
+    HIP_TRY(launch_extrapolate(u64, uprev, uprev2, w, N, p->stream));
+    p->sol_t[2] = p->sol_t[1];
+    p->sol_t[1] = p->sol_t[0];
+    p->sol_t[0] = tn;
+  } else if (p->sol_t[0] < 0) {
+    p->sol_t[0] = tn;
   }
-  if (tn != p->sol_t[0]) { p->sol_t[1] = p->sol_t[0]; p->sol_t[0] = tn; }
   // the solve's own copy of the temperature (von Mises reads it at the end)
   const double *theta = p->ptr<double>(p->r_theta[p->th_cur]);
   HIP_TRY(hipMemcpyAsync(p->ptr<double>(p->r_thsolve), theta, size_t(N) * 8, hipMemcpyDeviceToDevice, p->stream));
@@ -1270,7 +1287,7 @@ etm_status etm_plan_bind(etm_plan *p, void *ws, size_t bytes, void *stream) {
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->step = 0; p->cur = 0; p->th_cur = 0; p->rec = 0; p->n_thermal = 0;
   p->n_solves = 0; p->cg_iters = 0; p->cg_outer = 0; p->cg_total = 0; p->cg_relres = 0;
-  p->sol_t[0] = p->sol_t[1] = -1;
+  p->sol_t[0] = p->sol_t[1] = p->sol_t[2] = -1;
   p->host_status = ETM_OK;
   p->host_msg.clear();
   p->dinv_ready = false;
@@ -1437,6 +1454,8 @@ etm_status etm_write(etm_plan *p, int32_t field, const void *src, size_t bytes, 
     // the next solve's starting point comes from this displacement
     HIP_TRY(hipMemcpyAsync(p->ptr<double>(p->r_uprev64[field - ETM_FIELD_UX]), dstp, size_t(p->ntot) * 8,
                            hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->ptr<double>(p->r_uprev2_64[field - ETM_FIELD_UX]), dstp, size_t(p->ntot) * 8,
+                           hipMemcpyDeviceToDevice, p->stream));
   }
   HIP_TRY(hipStreamSynchronize(p->stream));
   return ETM_OK;
@@ -1462,7 +1481,7 @@ struct CkptHeader {
   int64_t step, rec, n_thermal, cg_total;
   int32_t cur, th_cur, prec, n_solves;
   int64_t ntot;
-  int64_t sol_t[2];
+  int64_t sol_t[3];
 };
 constexpr uint64_t kMagic = 0x45544d434b505431ull;
 
@@ -1482,6 +1501,7 @@ std::vector<const Region *> state_regions(const etm_plan *p) {
   r.push_back(&p->r_hist);
   for (int c = 0; c < 3; ++c) r.push_back(&p->r_u64[c]);
   for (int c = 0; c < 3; ++c) r.push_back(&p->r_uprev64[c]);
+  for (int c = 0; c < 3; ++c) r.push_back(&p->r_uprev2_64[c]);
   return r;
 }
 }  // namespace
@@ -1506,7 +1526,7 @@ etm_status etm_checkpoint(const etm_plan *p, void *dst, size_t bytes) {
   etm_checkpoint_size(p, &need);
   if (bytes < need) return fail(ETM_E_NOMEM, "checkpoint buffer too small");
   CkptHeader h{kMagic, p->step, p->rec, p->n_thermal, p->cg_total, p->cur, p->th_cur, p->prec, p->n_solves, p->ntot,
-               {p->sol_t[0], p->sol_t[1]}};
+               {p->sol_t[0], p->sol_t[1], p->sol_t[2]}};
   char *o = static_cast<char *>(dst);
   std::memcpy(o, &h, sizeof(h));
   o += sizeof(h);
@@ -1539,7 +1559,7 @@ etm_status etm_restore(etm_plan *p, const void *src, size_t bytes) {
   HIP_TRY(hipStreamSynchronize(p->stream));
   p->step = h.step; p->rec = h.rec; p->n_thermal = h.n_thermal; p->cg_total = h.cg_total;
   p->cur = h.cur; p->th_cur = h.th_cur; p->n_solves = h.n_solves;
-  p->sol_t[0] = h.sol_t[0]; p->sol_t[1] = h.sol_t[1];
+  p->sol_t[0] = h.sol_t[0]; p->sol_t[1] = h.sol_t[1]; p->sol_t[2] = h.sol_t[2];
   p->host_status = ETM_OK;
   p->joule_pending = false;
   p->a_base = kNoWaveBlock;

@@ -91,7 +91,7 @@ struct etm_plan {
   Region r_theta[2], r_theta32, r_psum, r_part, r_sc, r_hist;
   Region r_partm, r_scm, r_ctl, r_thsolve;  // the mechanical solve's partials, scalars, control block, temperature
   Region r_gR, r_gF;                        // its gate words (restart phase, finish phase)
-  Region r_u64[3], r_f64[3], r_r64[3], r_p64[3], r_w64[3], r_dinv64[3], r_uprev64[3];
+  Region r_u64[3], r_f64[3], r_r64[3], r_p64[3], r_w64[3], r_dinv64[3], r_uprev64[3], r_uprev2_64[3];
   Region r_u32[3], r_r32[3], r_p32[3], r_w32[3], r_dinv32[3], r_rhs32[3];
   Region r_vm, r_stage;
   // multigrid preconditioner of the mechanical CG
@@ -124,7 +124,7 @@ struct etm_plan {
   int64_t rec = 0;
   int64_t n_thermal = 0;
   int n_solves = 0, cg_iters = 0, cg_outer = 0;
-  int64_t sol_t[2] = {-1, -1};  // thermal-step count at the last two mechanical solves
+  int64_t sol_t[3] = {-1, -1, -1};  // thermal-step count at the last three mechanical solves
   int64_t cg_total = 0;
   double cg_relres = 0;
   etm_status host_status = ETM_OK;
