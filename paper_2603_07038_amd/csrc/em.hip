@@ -473,7 +473,8 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
         const int sl = dk < 0 ? s_m : dk > 0 ? s_p : s_0;
         return S.e[sl][c][ly + 1 + dj][lx + 1 + di];
       };
-      const uint8_t fl = (g.flags[n] & 7);
+      const uint8_t fla = g.flags[n], fl = fla & 7;
+      const bool sg = fla & kFlagSigma;
       const T e0x = E(0, 0, 0, 0), e0y = E(1, 0, 0, 0), e0z = E(2, 0, 0, 0);
       const bool pec_d[3] = {pec_j || pec_k, pec_i || pec_k, pec_i || pec_j};
       const T idz_k = T(G.idz[min(k, nz - 1)]), idz_m = T(G.idz[max(k - 1, 0)]), ihz_k = T(G.ihz[k]);
@@ -506,7 +507,7 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
           cc = (vi1 * hy_c - vi0 * hy_im) * ihx_i - (vj1 * hx_c - vj0 * hx_jm) * ihy_j;
         }
         const T e0 = D == 0 ? e0x : D == 1 ? e0y : e0z;
-        T er = cf[D * cs + n], a = cf[(3 + D) * cs + n], jd = T(0);
+        T er = cf[D * cs + n], a = sg ? cf[(3 + D) * cs + n] : T(0), jd = T(0);
         if (fl & (1 << D)) {
           const int q = find_port(L.ports, int64_t(D) * g.ntot + n);
           const PortTerm pt = port_terms(L.ports, q, step);
@@ -516,7 +517,7 @@ __device__ __forceinline__ void em_march_tile(const EmLaunch &L, const EmPtrs<T>
         const T inv = T(rcp64(double(er) + double(a)));
         p.oe[o] = (T(2) * er * e0 - c2 * cc - (er - a) * p.aux[o] - jd) * inv;
       }
-      if (acc_joule) {
+      if (acc_joule && sg) {
         const double az[2] = {G.azl[k], G.azh[k]};
         const double v[6] = {double(e0x), double(e0y), double(e0z), double(E(0, -1, 0, 0)), double(E(1, 0, -1, 0)),
                              double(E(2, 0, 0, -1))};
@@ -650,6 +651,8 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
   const bool fx = inb && j < ny;                   // x-normal (i, j, k), k < nz
   const bool fxm = inb && jm_ok;                   // x-normal (i, j - 1, k), k < nz
 
+  // (the coefficients and K are read whatever the node's flags: gating these
+  // loads on the flags measured slower here, unlike in the FP64 tile)
   auto load_node = [&](int kk, YeeNode &c) {
     const uint32_t n = uint32_t(kk) * sz + rj;
 #pragma unroll
@@ -661,7 +664,7 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
     }
     c.a2xm = 0.0f;  // from the previous lane
     c.a2ym = cf[4 * cs + uint32_t(kk) * sz + rm];
-    c.fl = g.flags[n] & 7;
+    c.fl = g.flags[n] & (7 | kFlagSigma);
   };
   struct Hold {
     float x, y, z, xm, zm;  // old faces at (i, j, k) and at (i, j - 1, k)
@@ -778,7 +781,7 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
     }
     // Joule power of e^n at the node, from its six incident edges
     const float a2xm = lane_prev(nd.a2[0]), exm = lane_prev(c0.x);
-    if (acc_joule && own) {
+    if (acc_joule && own && (nd.fl & kFlagSigma)) {
       const double a6[6] = {0.5 * double(nd.a2[0]), 0.5 * double(nd.a2[1]), 0.5 * double(nd.a2[2]),
                             i > 0 ? 0.5 * double(a2xm) : 0.0, jm_ok ? 0.5 * double(nd.a2ym) : 0.0,
                             k > 0 ? 0.5 * double(a2zm) : 0.0};

@@ -109,6 +109,13 @@ enum { kSolveRunning = 0, kSolveConverged = 1, kSolveGaveUp = 3 };
 
 // Reduction partials: per block, up to 4 doubles.
 constexpr int kRedWidth = 4;
+// Per-node flag bits besides the port bits (1 << d for a port on own edge d):
+// a cell around the node conducts (sigma0 != 0), so an edge incident to the
+// node may carry a loss term and Joule heat; such a cell's conductivity also
+// depends on temperature (tcr != 0), so the mixed path's K may be nonzero.
+// Without them every incident edge has a = 0 and K = 0, which the march
+// takes without reading them.
+constexpr uint8_t kFlagSigma = 8, kFlagTcr = 16;
 // Rows after a kernel's own partials that a two-stage reduction uses for its
 // first stage.
 constexpr int64_t kFinalizeRows = 512;

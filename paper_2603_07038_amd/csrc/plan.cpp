@@ -325,8 +325,24 @@ etm_status derive(etm_plan *p, const etm_source *src) {
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
       std::memcpy(&p->mat_pad[p->nidx(0, j, k)], &p->mat_nat[(size_t(k) * ny + j) * nx], nx);
-  // ports
+  // conducting (and temperature-dependent) cells mark their eight corner
+  // nodes: every edge incident to a node lies in the node's eight cells
   p->flags.assign(p->ntot, 0);
+  {
+    uint8_t mbits[256] = {};
+    for (int m = 0; m < p->n_mat; ++m)
+      if (p->mats[m].sigma0 != 0.0) mbits[m] = uint8_t(kFlagSigma | (p->mats[m].tcr != 0.0 ? kFlagTcr : 0));
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j) {
+        const uint8_t *row = &p->mat_nat[(size_t(k) * ny + j) * nx];
+        for (int i = 0; i < nx; ++i) {
+          const uint8_t b = mbits[row[i]];
+          if (!b) continue;
+          for (int c = 0; c < 8; ++c) p->flags[p->nidx(i + (c & 1), j + ((c >> 1) & 1), k + (c >> 2))] |= b;
+        }
+      }
+  }
+  // ports
   p->pe_key.clear(); p->pe_gs.clear(); p->pe_start.clear(); p->pw_wave.clear(); p->pw_wt.clear();
   if (src && src->n_ports > 0) {
     struct PE { int64_t key; int wave; double wt, g; };
