@@ -12,9 +12,12 @@
 // changes.  Every variant computes with the same per-node code as its solo
 // run, so its results are bitwise those of the solo run.
 //
-// The z-chunk length per variant comes from a tuning table keyed by the
-// variant's size class ("{\"kchunk\": {\"<log2 cells>\": k, ...}}"), written
-// by the package's autotuner; without an entry the automatic choice is used.
+// The tile shape per variant -- its z-chunk length and, in mixed precision,
+// its work layout (runs over the x-fastest plane or row segments) -- comes
+// from a tuning table keyed by the variant's size class
+// ("{\"kchunk\": {\"<log2 cells>\": k, ...}, \"layout\": {\"<log2 cells>\": 1 or 2}}"),
+// written by the package's autotuner; without an entry the automatic choice
+// is used.
 //
 // etm_batch_advance_noalloc runs the same steps with the same kernels but
 // allocates nothing: the descriptors, the work list and the step counter live
@@ -44,6 +47,7 @@ struct etm_batch {
   int32_t max_slots = 0;
   std::vector<etm_plan *> slots;
   std::map<int, int> kchunk_by_class;
+  std::map<int, int> layout_by_class;
   // device
   BatchVar *d_vars = nullptr;
   int4 *d_items = nullptr;
@@ -76,11 +80,13 @@ void drop_graphs(etm_batch *b) {
   b->graphs.clear();
 }
 
-// Minimal reader for {"kchunk": {"17": 8, ...}}.
-void parse_tune(const char *json, std::map<int, int> &out) {
+// Minimal reader of one integer map of the tuning table, e.g.
+// {"kchunk": {"17": 8, ...}}: entries with a value outside [lo, hi] are
+// ignored, as is anything malformed.
+void parse_tune(const char *json, const char *name, int lo, int hi, std::map<int, int> &out) {
   if (!json) return;
   const std::string s(json);
-  size_t p = s.find("\"kchunk\"");
+  size_t p = s.find(name);
   if (p == std::string::npos) return;
   p = s.find('{', p);
   if (p == std::string::npos) return;
@@ -93,7 +99,7 @@ void parse_tune(const char *json, std::map<int, int> &out) {
     if (q1 == std::string::npos || c == std::string::npos || c >= e) break;
     const int key = std::atoi(s.substr(q0 + 1, q1 - q0 - 1).c_str());
     const int val = std::atoi(s.c_str() + c + 1);
-    if (val >= 1 && val <= 128) out[key] = val;
+    if (val >= lo && val <= hi) out[key] = val;
     p = s.find(',', c);
     if (p == std::string::npos || p > e) break;
   }
@@ -113,6 +119,8 @@ void order_variants(etm_batch *b) {
     if (b->slots[s]) b->order.push_back(s);
   for (int slot : b->order) {
     etm_plan *p = b->slots[slot];
+    auto lt = b->layout_by_class.find(size_class(p));
+    p->layout = lt != b->layout_by_class.end() ? lt->second : kLayoutAuto;
     auto it = b->kchunk_by_class.find(size_class(p));
     p->kchunk = it != b->kchunk_by_class.end() ? it->second : em_kchunk(p->dev_grid(), b->precision);
   }
@@ -369,7 +377,8 @@ etm_status etm_batch_create(int32_t max_slots, const char *tune_json, etm_batch 
   b->order.reserve(max_slots);
   b->own.assign(max_slots, nullptr);
   b->old_cur.assign(max_slots, 0);
-  parse_tune(tune_json, b->kchunk_by_class);
+  parse_tune(tune_json, "\"kchunk\"", 1, 128, b->kchunk_by_class);
+  parse_tune(tune_json, "\"layout\"", kLayoutRuns, kLayoutRows, b->layout_by_class);
   hipError_t e = hipGetDevice(&b->device);
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_vars, sizeof(BatchVar) * max_slots);
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_ctr, sizeof(int64_t));
@@ -408,6 +417,7 @@ etm_status etm_batch_attach(etm_batch *b, etm_plan *p, int32_t *slot) {
 etm_status etm_batch_detach(etm_batch *b, int32_t slot) {
   if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot]) return fail(ETM_E_INVAL, "bad slot");
   b->slots[slot]->kchunk = 0;
+  b->slots[slot]->layout = kLayoutAuto;
   b->slots[slot] = nullptr;
   b->dirty = true;
   return ETM_OK;

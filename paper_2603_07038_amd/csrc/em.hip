@@ -565,10 +565,13 @@ constexpr int WX = 62;
 // Rows shorter than this are marched as runs over the x-fastest plane (no
 // idle lanes at row ends); longer rows in tiles of BY rows, whose waves read
 // each other's rows j +- 1 from the same L2 lines.  Measured on gfx950: the
-// runs take the 256x256x64 slice from 125 to 113 us per step, the tiles
-// keep the 1024x1024x128 package at 3.23 ms (3.35 ms as runs).
-constexpr int kRunMaxRow = 512;
-__host__ __device__ inline bool em_runs(int nx) { return nx + 1 < kRunMaxRow; }
+// runs take the 256x256x64 slice from 125 to 113 us per step and a
+// 608x608x64 package from 743 to 674 us, the tiles keep the 1024x1024x128
+// package at 3.23 ms (3.35 ms as runs).
+constexpr int kRunMaxRow = 1024;
+__host__ __device__ inline bool em_runs(const DevGrid &g) {
+  return g.layout == kLayoutRuns || (g.layout != kLayoutRows && g.nx + 1 < kRunMaxRow);
+}
 
 __device__ __forceinline__ float lane_next(float v) {  // value of lane + 1 (0 past the last lane)
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
@@ -601,7 +604,7 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
   const int nx1 = nx + 1, nplane = nx1 * (ny + 1);
   int tc;
   bool inb;
-  if (em_runs(nx)) {
+  if (em_runs(g)) {
     const int w = ts * BY + wave;
     if (WX * w >= nplane) return;  // the whole wave is past the plane
     const int t = WX * w - 1 + lane;
@@ -940,6 +943,9 @@ __global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const 
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   if (i > g.nx || j > g.ny) return;
   const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
+  // after a temperature change only edges next to a cell whose sigma depends
+  // on it change (eps_r never does)
+  if (ck.tcr_only && !(g.flags[n] & kFlagTcr)) return;
   const double ax[2] = {g.al[0][i], g.ah[0][i]}, ay[2] = {g.al[1][j], g.ah[1][j]}, az[2] = {g.al[2][k], g.ah[2][k]};
   LCell CL;
   CL.M = &MT;
@@ -1222,7 +1228,7 @@ __global__ void fill_kernel(uint32_t *dst, int64_t n_words) {
 }  // namespace
 
 void em_tiles(const DevGrid &g, int precision, int kchunk, int *ntx, int *nty, int *nkc) {
-  if (precision == ETM_PREC_MIXED && em_runs(g.nx)) {
+  if (precision == ETM_PREC_MIXED && em_runs(g)) {
     // BY runs of WX nodes of the x-fastest plane per block, one row of blocks
     const int64_t plane = int64_t(g.nx + 1) * (g.ny + 1), per = int64_t(WX) * BY;
     *ntx = int((plane + per - 1) / per);
@@ -1379,7 +1385,8 @@ hipError_t launch_coef(const DevGrid &g, const DevPorts &P, int precision, const
                        hipStream_t s) {
   const dim3 grid = node_grid(g), block(BX, BY, 1);
   if (precision == ETM_PREC_FP64)
-    hipLaunchKernelGGL((coef_kernel<double>), grid, block, 0, s, g, P, (const double *)theta, (double *)coef, CoefK{});
+    hipLaunchKernelGGL((coef_kernel<double>), grid, block, 0, s, g, P, (const double *)theta, (double *)coef,
+                       CoefK{nullptr, nullptr, nullptr, ck.tcr_only});
   else
     hipLaunchKernelGGL((coef_kernel<float>), grid, block, 0, s, g, P, (const float *)theta, (float *)coef, ck);
   return hipGetLastError();

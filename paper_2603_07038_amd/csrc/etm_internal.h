@@ -50,7 +50,13 @@ struct DevGrid {
   const uint8_t *flags;           // per node: bit d = the d-edge from this node is a port edge
   const double *mtab;             // n_mat rows of kMatStride
   int pec;                        // bit f = face f (-x,+x,-y,+y,-z,+z) is PEC
+  int layout;                     // mixed march waves: kLayoutAuto (by row length), kLayoutRuns, kLayoutRows
 };
+// Work layouts of the mixed-precision march: a wave takes a run of 62
+// consecutive nodes of the plane numbered x fastest, or a 62-node segment of
+// one row (4 rows per block); automatic picks runs for rows shorter than 512
+// nodes.  Results are bitwise the same in every layout.
+enum { kLayoutAuto = 0, kLayoutRuns = 1, kLayoutRows = 2 };
 
 // A closed-form wave as stored on the device: kind, n_pulses, amp, t0,
 // width, freq, t_on, t_off, pulse centres.  The waves are sampled on the
@@ -162,6 +168,7 @@ hipError_t launch_wave_sample(const double *aw, int n, double dt, int64_t base, 
 struct CoefK {
   float *K = nullptr;
   const float *e_cur = nullptr, *e_prev = nullptr;
+  int tcr_only = 0;  // a refresh after a temperature change: only nodes with kFlagTcr can change
 };
 hipError_t launch_coef(const DevGrid &g, const DevPorts &P, int precision, const void *theta, void *coef, CoefK ck,
                        hipStream_t s);

@@ -626,6 +626,7 @@ etm_status coef_refresh(etm_plan *p, bool update_k) {
   const void *th = p->prec == ETM_PREC_MIXED ? (const void *)p->ptr<float>(p->r_theta32)
                                              : (const void *)p->ptr<double>(p->r_theta[p->th_cur]);
   CoefK ck;
+  ck.tcr_only = update_k ? 1 : 0;
   if (update_k && p->prec == ETM_PREC_MIXED) {
     ck.K = p->ptr<float>(p->r_K[0]);
     ck.e_cur = p->ptr<float>(p->r_e[p->cur][0]);

@@ -132,6 +132,7 @@ struct etm_plan {
   bool dinv_ready = false;
   bool joule_pending = false;  // Joule power of the current field not yet in psum
   int kchunk = 0;              // z planes per EM block (0 = automatic)
+  int layout = 0;              // mixed march work layout (kLayoutAuto unless a batch's tuning table sets it)
   int64_t comp_stride = 0;     // elements between the x, y, z components of a field
   bool has_tcr = false;        // some conducting material has a temperature coefficient
 
@@ -158,6 +159,7 @@ struct etm_plan {
     int pec = 0;
     for (int f = 0; f < 6; ++f) if (opts.em_bc[f] == ETM_PEC) pec |= 1 << f;
     g.pec = pec;
+    g.layout = layout;
     return g;
   }
   DevPorts dev_ports() const {

@@ -1,16 +1,23 @@
-"""Autotuner for the batched EM march: the z-chunk (tile height) per size class.
+"""Autotuner for the batched EM march: the tile shape per size class.
 
     python -m paper_2603_07038_amd.tune [--out FILE] [--classes 15-24] [--steps 64]
 
-The batched march works on tiles of 4 node rows (64 nodes wide in FP64, 62
-in mixed precision) cut into z-chunks of ``kchunk`` node planes.  Short chunks give more work items (better load
-balance when few variants are attached) but stage two extra planes per
-chunk; long chunks amortise the halo.  For each size class (floor of log2 of
-the cell count, the key the batch uses) a package variant of that size is
-replicated until the batch holds at least 16 M cells, and every candidate
-chunk is timed over graph-replayed EM steps.  The fastest per class is
-written as ``{"kchunk": {"<class>": k, ...}, "timings_us": {...}}``, the
-table ``Batch`` reads (``tune_gfx950.json`` next to this file by default).
+The batched march works on tiles of 4 waves, cut into z-chunks of
+``kchunk`` node planes.  In mixed precision a wave takes either a run of 62
+consecutive nodes of the plane numbered x fastest (layout 1) or a 62-node
+segment of one row, 4 rows per block (layout 2); in FP64 a tile is 64 x 4
+nodes staged in LDS.  Short chunks give more work items (better load balance
+when few variants are attached) but stage extra planes per chunk; long
+chunks amortise the halo.  Runs leave no lanes idle at row ends; row
+segments share the rows j - 1, j + 1 of their neighbours in L2.  For each
+size class (floor of log2 of the cell count, the key the batch uses) a
+package variant of that size is replicated until the batch holds at least
+16 M cells, and every candidate (layout, chunk) is timed over graph-replayed
+EM steps.  The fastest per class is written as
+``{"kchunk": {"<class>": k, ...}, "layout": {"<class>": 1 or 2, ...},
+"timings_us": {...}}``, the table ``Batch`` reads (``tune_gfx950.json`` next
+to this file by default).  Every layout and chunk gives bitwise the same
+results, so the table changes speed only.
 """
 from __future__ import annotations
 
@@ -23,6 +30,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tune_gfx950.json")
 CANDIDATES = (2, 4, 6, 8, 12, 16, 24, 32)
+LAYOUTS = (1, 2)  # mixed precision: runs over the x-fastest plane, row segments
 
 
 def class_problem(c: int):
@@ -37,30 +45,39 @@ def class_problem(c: int):
 
 def time_class(c: int, steps: int, precision: int):
     import torch
-    from . import Batch, Plan, cfl_dt
+    from . import ETM_PREC_MIXED, Batch, Plan, cfl_dt
     p = class_problem(c)
     assert int(math.floor(math.log2(p.n_cells))) == c, (c, p.n_cells)
     copies = max(1, min(32, (16 << 20) // p.n_cells))
     dt = cfl_dt(p)
     J = p.sample_J_half(dt, 4 * steps)
+    layouts = LAYOUTS if precision == ETM_PREC_MIXED else (0,)
+    plans = [Plan(p, J, dt=dt, precision=precision, n_steps=4 * steps, history=False) for _ in range(copies)]
     res = {}
-    for kc in CANDIDATES:
-        if kc > p.nz + 1 and kc != CANDIDATES[0]:
-            continue
-        b = Batch(copies + 1, json.dumps({"kchunk": {str(c): kc}}))
-        plans = [Plan(p, J, dt=dt, precision=precision, n_steps=4 * steps, history=False) for _ in range(copies)]
-        for pl in plans:
-            b.attach(pl)
-        s = torch.cuda.Stream()
-        b.advance(steps, s)  # warm-up: captures the graph of this segment length
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        b.advance(steps, s)
-        e1.record(s)
-        e1.synchronize()
-        res[kc] = e0.elapsed_time(e1) * 1e3 / steps
-        del b, plans
-        torch.cuda.synchronize()
+    for lay in layouts:
+        for kc in CANDIDATES:
+            if kc > p.nz + 1 and kc != CANDIDATES[0]:
+                continue
+            table = {"kchunk": {str(c): kc}}
+            if lay:
+                table["layout"] = {str(c): lay}
+            b = Batch(copies + 1, json.dumps(table))
+            for pl in plans:
+                b.attach(pl)
+            s = torch.cuda.Stream()
+            b.advance(steps, s)  # warm-up: captures the graph of this segment length
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            b.advance(steps, s)
+            e1.record(s)
+            e1.synchronize()
+            res[(lay, kc)] = e0.elapsed_time(e1) * 1e3 / steps
+            for slot in range(copies):
+                b.detach(slot)
+            del b
+            torch.cuda.synchronize()
+    del plans
+    torch.cuda.synchronize()
     return res, copies, p.n_cells
 
 
@@ -74,14 +91,17 @@ def main(argv=None):
     from . import ETM_PREC_FP64, ETM_PREC_MIXED
     prec = ETM_PREC_MIXED if a.precision == "mixed" else ETM_PREC_FP64
     lo, hi = (int(x) for x in a.classes.split("-"))
-    table = {"kchunk": {}, "timings_us": {}, "precision": a.precision, "candidates": list(CANDIDATES)}
+    table = {"kchunk": {}, "layout": {}, "timings_us": {}, "precision": a.precision, "candidates": list(CANDIDATES)}
     for c in range(lo, hi + 1):
         res, copies, cells = time_class(c, a.steps, prec)
-        best = min(res, key=res.get)
-        table["kchunk"][str(c)] = best
-        table["timings_us"][str(c)] = {str(k): round(v, 2) for k, v in res.items()}
-        print(json.dumps({"class": c, "cells": cells, "copies": copies, "best": best,
-                          "us_per_step": {k: round(v, 1) for k, v in res.items()}}), flush=True)
+        lay, kc = min(res, key=res.get)
+        table["kchunk"][str(c)] = kc
+        if lay:
+            table["layout"][str(c)] = lay
+        table["timings_us"][str(c)] = {f"{'runs' if l == 1 else 'rows' if l == 2 else 'tile'}/{k}": round(v, 2)
+                                      for (l, k), v in res.items()}
+        print(json.dumps({"class": c, "cells": cells, "copies": copies, "best": [lay, kc],
+                          "us_per_step": table["timings_us"][str(c)]}), flush=True)
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1)
     print("wrote", a.out)

@@ -152,6 +152,8 @@ int main() {
       nullptr, "", "{}", "{\"kchunk\": {\"17\": 8, \"33\": 16}}", "{\"kchunk\": {\"17\": 8, ",
       "{\"kchunk\"", "{\"kchunk\": {", "{\"kchunk\": {\"", "{\"kchunk\": {\"5\"", "{\"kchunk\": {\"5\":",
       "{\"kchunk\": {\"5\": 999, \"6\": -1, \"x\": \"y\"}}", "\"kchunk\":}", "{\"kchunk\": {\"1\": 4}, \"kchunk\": 3}",
+      "{\"kchunk\": {\"17\": 8}, \"layout\": {\"17\": 2, \"18\": 1, \"19\": 7}}", "{\"layout\": {\"",
+      "{\"layout\"", "{\"layout\": {\"3\": }",
   };
   for (const char *t : tunes) {
     etm_batch *b = reinterpret_cast<etm_batch *>(0x1);

@@ -1,6 +1,7 @@
 """Batched variants: each variant's fields after a batched run are bitwise
 those of its solo run, for both precisions, with uneven sizes, thermal
 blocks inside the run and graph-replayed segments."""
+import json
 import sys
 
 import numpy as np
@@ -26,10 +27,17 @@ def _state(plan):
                                    etm.ETM_FIELD_PSUM)]
 
 
-@pytest.mark.parametrize("prec", [etm.ETM_PREC_FP64, etm.ETM_PREC_MIXED])
-def test_batch_matches_solo_bitwise(prec):
+def _size_class(p):
+    return int(np.floor(np.log2(p.n_cells)))
+
+
+@pytest.mark.parametrize("prec,layout", [(etm.ETM_PREC_FP64, None), (etm.ETM_PREC_MIXED, None),
+                                         (etm.ETM_PREC_MIXED, 1), (etm.ETM_PREC_MIXED, 2)])
+def test_batch_matches_solo_bitwise(prec, layout):
+    """layout None: the default tuning table; 1 / 2: every variant forced to
+    runs over the x-fastest plane / row segments (with odd z-chunks)."""
     probs = _variants(5)
-    print(f"[batch] prec={prec} variants={[p.name for p in probs]}", flush=True)
+    print(f"[batch] prec={prec} layout={layout} variants={[p.name for p in probs]}", flush=True)
     dts = [etm.cfl_dt(p) for p in probs]
     Js = [p.sample_J_half(dt, 60) for p, dt in zip(probs, dts)]
     solo = []
@@ -38,7 +46,12 @@ def test_batch_matches_solo_bitwise(prec):
         pl.advance(23)
         pl.advance(37)
         solo.append(_state(pl))
-    b = etm.Batch(8)
+    if layout is None:
+        b = etm.Batch(8)
+    else:
+        classes = sorted({_size_class(p) for p in probs})
+        b = etm.Batch(8, json.dumps({"kchunk": {str(c): [3, 5, 2][c % 3] for c in classes},
+                                     "layout": {str(c): layout for c in classes}}))
     plans = []
     for p, dt, J in zip(probs, dts, Js):
         pl = etm.Plan(p, J, dt=dt, precision=prec, n_steps=60, history=False)
