@@ -198,11 +198,13 @@ struct GTcr {
   const double *mtab;
   __device__ __forceinline__ double operator()(int m) const { return mtab[m * kMatStride + MC_TCR]; }
 };
-template <typename T>
-struct GTh {
-  const T *th;
-  int64_t n, sy, sz;
-  __device__ __forceinline__ double operator()(int di, int dj, int dk) const { return double(th[n + di + dj * sy + dk * sz]); }
+// The temperatures an own edge of the node reads, loaded beforehand: the
+// node's and its +x, +y, +z neighbours'.
+struct PTh {
+  double t[4];
+  __device__ __forceinline__ double operator()(int di, int dj, int dk) const {
+    return di > 0 ? t[1] : dj > 0 ? t[2] : dk > 0 ? t[3] : t[0];
+  }
 };
 
 // The per-material EM constants in LDS: eps_r, the scaled conductance
@@ -920,6 +922,24 @@ __device__ __forceinline__ void block_reduce_store(const double (&sums)[NS], con
 
 inline dim3 node_grid(const DevGrid &g) { return dim3((g.nx + 1 + BX - 1) / BX, (g.ny + 1 + BY - 1) / BY, g.nz + 1); }
 
+// Node tiles of BX x BY nodes of one plane, one block each, as a 1D grid
+// whose logical tile t = (tile row * tiles per row + tile) * planes + k runs
+// through the planes of one column of tiles first; each XCD takes a
+// contiguous range of t.  The blocks that read a plane's values as their z
+// neighbours then run beside the block that owns it, on the same L2.
+inline dim3 node_grid_z(const DevGrid &g) {
+  const dim3 d = node_grid(g);
+  return dim3(d.x * d.y * d.z);
+}
+__device__ __forceinline__ void node_tile_z(const DevGrid &g, int &i, int &j, int &k) {
+  const int nbx = (g.nx + 1 + BX - 1) / BX, nk = g.nz + 1;
+  const int t = xcd_remap(int(blockIdx.x), int(gridDim.x));
+  k = t % nk;
+  const int c = t / nk;
+  i = (c % nbx) * BX + int(threadIdx.x);
+  j = (c / nbx) * BY + int(threadIdx.y);
+}
+
 // Joule of the current field (the deferred last step) at node (i,j,k), with
 // the same arithmetic as the march kernel (missing low-side edges read 0).
 template <typename T>
@@ -939,13 +959,17 @@ __device__ __forceinline__ double pending_joule(const DevGrid &g, const T *const
 template <typename T>
 __global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const T *th, T *cf, CoefK ck) {
   __shared__ LdsMat MT;
-  lds_mat_load(g, MT);
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  if (i > g.nx || j > g.ny) return;
-  const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
+  int i, j, k;
+  node_tile_z(g, i, j, k);
+  const bool in = i <= g.nx && j <= g.ny;
+  const int64_t n = in ? int64_t(k) * g.sz + int64_t(j) * g.sy + i : 0;
   // after a temperature change only edges next to a cell whose sigma depends
-  // on it change (eps_r never does)
-  if (ck.tcr_only && !(g.flags[n] & kFlagTcr)) return;
+  // on it change (eps_r never does); a block without such a node leaves
+  // before it loads the material table
+  const bool work = in && (!ck.tcr_only || (g.flags[n] & kFlagTcr));
+  if (!__syncthreads_or(work)) return;
+  lds_mat_load(g, MT);
+  if (!work) return;
   const double ax[2] = {g.al[0][i], g.ah[0][i]}, ay[2] = {g.al[1][j], g.ah[1][j]}, az[2] = {g.al[2][k], g.ah[2][k]};
   LCell CL;
   CL.M = &MT;
@@ -957,13 +981,29 @@ __global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const 
     CL.id[q] = ok ? int(g.mat[n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz]) : 0;
   }
   const LTcr TC{&MT};
-  GTh<T> TH{th, n, g.sy, g.sz};
   const bool ex[3] = {i < g.nx, j < g.ny, k < g.nz};
+  // every load up front: the temperatures the own edges may read and, for a
+  // K update, the old 2a, K and the two fields (clamped where an edge does
+  // not exist), so none waits behind a branch
+  const PTh TH{{double(th[n]), double(th[ex[0] ? n + 1 : n]), double(th[ex[1] ? n + g.sy : n]),
+                double(th[ex[2] ? n + g.sz : n])}};
+  const uint32_t cs = g.cs;
+  float a2o[3] = {0.0f, 0.0f, 0.0f}, Ko[3] = {0.0f, 0.0f, 0.0f}, ec[3] = {0.0f, 0.0f, 0.0f},
+        ep[3] = {0.0f, 0.0f, 0.0f};
+  if (sizeof(T) == 4 && ck.K) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const uint32_t o = d * cs + uint32_t(n);
+      a2o[d] = float(cf[(3 + d) * cs + n]);
+      Ko[d] = ck.K[o];
+      ec[d] = ck.e_cur[o];
+      ep[d] = ck.e_prev[o];
+    }
+  }
   double er[3] = {1.0, 1.0, 1.0}, a[3] = {0.0, 0.0, 0.0};
   if (ex[0]) a[0] = edge_coef<0>(1, ax, ay, az, CL, TC, TH, &er[0]);
   if (ex[1]) a[1] = edge_coef<1>(1, ax, ay, az, CL, TC, TH, &er[1]);
   if (ex[2]) a[2] = edge_coef<2>(1, ax, ay, az, CL, TC, TH, &er[2]);
-  const uint32_t cs = g.cs;
   const uint8_t fl = g.flags[n];
   for (int d = 0; d < 3; ++d) {
     const double e = er[d] > 0.0 ? er[d] : 1.0;  // an edge without cells keeps a harmless 1
@@ -972,11 +1012,9 @@ __global__ __launch_bounds__(256) void coef_kernel(DevGrid g, DevPorts P, const 
       if (ck.K && ex[d]) {
         // leapfrog form: a changed from a_old to a between e_prev = e^{n-1}
         // and e_cur = e^n; K += (a - a_old) (e^n + e^{n-1})
-        const float a2o = float(cf[(3 + d) * cs + n]);
-        if (a2 != a2o) {
+        if (a2 != a2o[d]) {
           const uint32_t o = d * cs + uint32_t(n);
-          ck.K[o] = float(double(ck.K[o]) +
-                          0.5 * (double(a2) - double(a2o)) * (double(ck.e_cur[o]) + double(ck.e_prev[o])));
+          ck.K[o] = float(double(Ko[d]) + 0.5 * (double(a2) - double(a2o[d])) * (double(ec[d]) + double(ep[d])));
         }
       }
       cf[d * cs + n] = T(e);
@@ -1011,73 +1049,129 @@ __device__ __forceinline__ void lds_therm_load(const DevGrid &g, LdsTherm &M) {
   __syncthreads();
 }
 
-__device__ __forceinline__ void thermal_node(const ThermalLaunch &L, const LdsTherm &M, int i, int j, int k,
-                                             int64_t n, double ps, double &e_part, double &m_part) {
-  const DevGrid &g = L.g;
-  const double t0 = L.theta_in[n];
+// The thermal step of node (i, j, k) in two parts: every load is issued
+// first (out-of-mesh neighbours, cells and edges read the node's own entry
+// at a clamped index and are masked to zero afterwards, so no load sits
+// behind a branch), then the arithmetic, in the same order as with branches
+// (adding the masked zeros leaves the sums unchanged).
+struct ThermIn {
+  double dxs[2], dys[2], dzs[2], ixs[2], iys[2], izs[2], V;
   int id[8];
+  double t0, txl, txh, tyl, tyh, tzl, tzh, ps;
+  double ax[2], ay[2], az[2], a6[6], v[6];
+};
+template <typename T>
+__device__ __forceinline__ void thermal_load(const ThermalLaunch &L, const T *const *e, const T *cf, int i, int j,
+                                             int k, int64_t n, ThermIn &q) {
+  const DevGrid &g = L.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int64_t sy = g.sy, sz = g.sz;
+  const bool xl = i > 0, xh = i < nx, yl = j > 0, yh = j < ny, zl = k > 0, zh = k < nz;
+  const int il = xl ? i - 1 : 0, ih = xh ? i : nx - 1, jl = yl ? j - 1 : 0, jh = yh ? j : ny - 1;
+  const int kl = zl ? k - 1 : 0, kh = zh ? k : nz - 1;
+  q.dxs[0] = g.dx[il]; q.dxs[1] = g.dx[ih]; q.dys[0] = g.dy[jl]; q.dys[1] = g.dy[jh];
+  q.dzs[0] = g.dz[kl]; q.dzs[1] = g.dz[kh];
+  q.ixs[0] = g.idx[il]; q.ixs[1] = g.idx[ih]; q.iys[0] = g.idy[jl]; q.iys[1] = g.idy[jh];
+  q.izs[0] = g.idz[kl]; q.izs[1] = g.idz[kh];
+  q.V = g.hx[i] * g.hy[j] * g.hz[k];
+  const bool vx[2] = {xl, xh}, vy[2] = {yl, yh}, vz[2] = {zl, zh};
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-    const int ii = i - 1 + ox, jj = j - 1 + oy, kk = k - 1 + oz;
-    const bool ok = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
-    id[c] = ok ? int(g.mat[n + (ox - 1) + (oy - 1) * g.sy + (oz - 1) * g.sz]) : -1;
+    const bool ok = vx[ox] && vy[oy] && vz[oz];
+    const int m = int(g.mat[ok ? n + (ox - 1) + (oy - 1) * sy + (oz - 1) * sz : n]);
+    q.id[c] = ok ? m : -1;
+  }
+  q.t0 = L.theta_in[n];
+  q.txl = L.theta_in[xl ? n - 1 : n]; q.txh = L.theta_in[xh ? n + 1 : n];
+  q.tyl = L.theta_in[yl ? n - sy : n]; q.tyh = L.theta_in[yh ? n + sy : n];
+  q.tzl = L.theta_in[zl ? n - sz : n]; q.tzh = L.theta_in[zh ? n + sz : n];
+  q.ps = L.psum[n];
+  if (L.acc_joule) {
+    // the pending Joule power of the current field (as joule_from_coef)
+    const uint32_t cs = g.cs;
+    const double h = sizeof(T) == 4 ? 0.5 : 1.0;
+    q.ax[0] = g.al[0][i]; q.ax[1] = g.ah[0][i]; q.ay[0] = g.al[1][j]; q.ay[1] = g.ah[1][j];
+    q.az[0] = g.al[2][k]; q.az[1] = g.ah[2][k];
+    const double exl = double(e[0][xl ? n - 1 : n]), eyl = double(e[1][yl ? n - sy : n]),
+                 ezl = double(e[2][zl ? n - sz : n]);
+    const double a3 = double(cf[3 * cs + (xl ? n - 1 : n)]), a4 = double(cf[4 * cs + (yl ? n - sy : n)]),
+                 a5 = double(cf[5 * cs + (zl ? n - sz : n)]);
+    q.v[0] = double(e[0][n]); q.v[1] = double(e[1][n]); q.v[2] = double(e[2][n]);
+    q.v[3] = xl ? exl : 0.0; q.v[4] = yl ? eyl : 0.0; q.v[5] = zl ? ezl : 0.0;
+    q.a6[0] = h * double(cf[3 * cs + n]); q.a6[1] = h * double(cf[4 * cs + n]); q.a6[2] = h * double(cf[5 * cs + n]);
+    q.a6[3] = xl ? h * a3 : 0.0; q.a6[4] = yl ? h * a4 : 0.0; q.a6[5] = zl ? h * a5 : 0.0;
+  }
+}
+
+__device__ __forceinline__ void thermal_node(const ThermalLaunch &L, const LdsTherm &M, const ThermIn &q, int i,
+                                             int j, int k, int64_t n, double &e_part, double &m_part) {
+  const DevGrid &g = L.g;
+  double ps = q.ps;
+  if (L.acc_joule) {
+    const double P = node_joule(q.a6, q.ax, q.ay, q.az, q.v, L.jf);
+    if (P != 0.0) ps += P;
   }
   double CV = 0.0, gx0 = 0, gx1 = 0, gy0 = 0, gy1 = 0, gz0 = 0, gz1 = 0;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    if (id[c] < 0) continue;
     const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-    const int ii = i - 1 + ox, jj = j - 1 + oy, kk = k - 1 + oz;
-    const double ddx = g.dx[ii], ddy = g.dy[jj], ddz = g.dz[kk], kc = M.k[id[c]];
-    CV += M.rc[id[c]] * 0.125 * ddx * ddy * ddz;
-    const double wx = 0.25 * ddy * ddz * kc * g.idx[ii], wy = 0.25 * ddx * ddz * kc * g.idy[jj],
-                 wz = 0.25 * ddx * ddy * kc * g.idz[kk];
-    if (ox) gx1 += wx; else gx0 += wx;
-    if (oy) gy1 += wy; else gy0 += wy;
-    if (oz) gz1 += wz; else gz0 += wz;
+    const bool ok = q.id[c] >= 0;
+    const int m = ok ? q.id[c] : 0;
+    const double ddx = q.dxs[ox], ddy = q.dys[oy], ddz = q.dzs[oz], kc = M.k[m];
+    const double cv = M.rc[m] * 0.125 * ddx * ddy * ddz;
+    const double wx = 0.25 * ddy * ddz * kc * q.ixs[ox], wy = 0.25 * ddx * ddz * kc * q.iys[oy],
+                 wz = 0.25 * ddx * ddy * kc * q.izs[oz];
+    if (ok) {
+      CV += cv;
+      if (ox) gx1 += wx; else gx0 += wx;
+      if (oy) gy1 += wy; else gy0 += wy;
+      if (oz) gz1 += wz; else gz0 += wz;
+    }
   }
+  const double t0 = q.t0;
   double flux = 0.0;
-  if (i > 0) flux += gx0 * (t0 - L.theta_in[n - 1]);
-  if (i < g.nx) flux += gx1 * (t0 - L.theta_in[n + 1]);
-  if (j > 0) flux += gy0 * (t0 - L.theta_in[n - g.sy]);
-  if (j < g.ny) flux += gy1 * (t0 - L.theta_in[n + g.sy]);
-  if (k > 0) flux += gz0 * (t0 - L.theta_in[n - g.sz]);
-  if (k < g.nz) flux += gz1 * (t0 - L.theta_in[n + g.sz]);
-  const double V = g.hx[i] * g.hy[j] * g.hz[k];
-  const double tn = t0 + (L.dt * ps * V - double(L.R) * L.dt * flux) / CV;
+  if (i > 0) flux += gx0 * (t0 - q.txl);
+  if (i < g.nx) flux += gx1 * (t0 - q.txh);
+  if (j > 0) flux += gy0 * (t0 - q.tyl);
+  if (j < g.ny) flux += gy1 * (t0 - q.tyh);
+  if (k > 0) flux += gz0 * (t0 - q.tzl);
+  if (k < g.nz) flux += gz1 * (t0 - q.tzh);
+  const double tn = t0 + (L.dt * ps * q.V - double(L.R) * L.dt * flux) / CV;
   L.theta_out[n] = tn;
   L.psum[n] = 0.0;
   if (L.theta32) L.theta32[n] = float(tn);
-  e_part = L.dt * ps * V;
+  e_part = L.dt * ps * q.V;
   m_part = tn;
 }
 
-// One thread per node, one block per 64 x 4 node tile of a plane.
+// One thread per node, one block per 64 x 4 node tile of a plane (node_tile_z
+// order).  The node's loads are issued before the block loads the material
+// table into LDS and meets at the barrier.
 template <typename T>
 __global__ __launch_bounds__(256) void thermal_kernel(ThermalLaunch L, const T *e0, const T *e1, const T *e2,
                                                       const T *cf) {
   __shared__ LdsTherm MT;
-  lds_therm_load(L.g, MT);
   const DevGrid &g = L.g;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  int i, j, k;
+  node_tile_z(g, i, j, k);
+  const bool in = i <= g.nx && j <= g.ny;
+  const int64_t n = in ? int64_t(k) * g.sz + int64_t(j) * g.sy + i : 0;
+  ThermIn q;
+  if (in) {
+    const T *e[3] = {e0, e1, e2};
+    thermal_load<T>(L, e, cf, i, j, k, n, q);
+  }
+  lds_therm_load(g, MT);
   double e_part = 0.0, m_part = -1.0e300;
-  if (i <= g.nx && j <= g.ny) {
-    const int64_t n = int64_t(k) * g.sz + int64_t(j) * g.sy + i;
-    double ps = L.psum[n];
-    if (L.acc_joule) {
-      const T *e[3] = {e0, e1, e2};
-      const double P = pending_joule<T>(g, e, cf, i, j, k, n, L.jf);
-      if (P != 0.0) ps += P;
-    }
-    thermal_node(L, MT, i, j, k, n, ps, e_part, m_part);
+  if (in) {
+    thermal_node(L, MT, q, i, j, k, n, e_part, m_part);
     // the max reduction (fmax) drops NaN: carry a non-finite temperature
     // in the energy sum, which the finalize kernel checks
     if (!isfinite(m_part)) e_part = m_part - m_part;
   }
   const double s[1] = {e_part}, m[1] = {m_part};
-  const int64_t b = (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  block_reduce_store<1, 1>(s, m, L.partials + b * kRedWidth);
+  block_reduce_store<1, 1>(s, m, L.partials + int64_t(blockIdx.x) * kRedWidth);
 }
 
 // Add the pending Joule power of the current field to psum.
@@ -1348,7 +1442,7 @@ hipError_t launch_step_ctr(int64_t *ctr, int64_t v, int set, hipStream_t s) {
 }
 
 hipError_t launch_thermal(const ThermalLaunch &L, hipStream_t s) {
-  const dim3 grid = node_grid(L.g), block(BX, BY, 1);
+  const dim3 grid = node_grid_z(L.g), block(BX, BY, 1);
   if (L.precision == ETM_PREC_FP64)
     hipLaunchKernelGGL((thermal_kernel<double>), grid, block, 0, s, L, (const double *)L.e[0], (const double *)L.e[1],
                        (const double *)L.e[2], (const double *)L.coef);
@@ -1383,7 +1477,7 @@ hipError_t launch_joule_flush(const DevGrid &g, int precision, const void *const
 
 hipError_t launch_coef(const DevGrid &g, const DevPorts &P, int precision, const void *theta, void *coef, CoefK ck,
                        hipStream_t s) {
-  const dim3 grid = node_grid(g), block(BX, BY, 1);
+  const dim3 grid = node_grid_z(g), block(BX, BY, 1);
   if (precision == ETM_PREC_FP64)
     hipLaunchKernelGGL((coef_kernel<double>), grid, block, 0, s, g, P, (const double *)theta, (double *)coef,
                        CoefK{nullptr, nullptr, nullptr, ck.tcr_only});
