@@ -150,7 +150,8 @@ __device__ __forceinline__ void hex8_cell(T ux[8], T uy[8], T uz[8], T hx, T hy,
 // cell's K_e and stores the 24 results in LDS, and each owned node adds the
 // corners of its four cells in a fixed order, so y is deterministic.
 // Fixed DOFs give zero rows; x is taken as zero on them.  The next x plane
-// and the material id of the cell below it are fetched one layer ahead; the
+// and the material id of the cell below it are fetched one layer ahead,
+// right after the layer's first barrier; the
 // Lame constants come from a per-block LDS copy of the material table (mu
 // stored as -1 for a void material), so no global load sits between the
 // barrier and the cell work.  The epilogue's own inputs (Epi::load) and the
@@ -237,7 +238,12 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
   fetch(k0);
   for (int ck = k0 - 1; ck < k1; ++ck) {
     stage(ck + 1);        // plane ck + 1 (fetched during the previous layer)
-    if (ck + 2 <= k1) fetch(ck + 2);  // in flight while this layer computes
+    const int m = mid;    // cell layer ck (staged with plane ck + 1)
+    const T hz = m >= 0 ? T(g.dz[ck]) : T(1);
+    __syncthreads();
+    // issued after the barrier (which waits for every load in flight), so
+    // they are in flight while this layer computes
+    if (ck + 2 <= k1) fetch(ck + 2);
     const int64_t n = int64_t(ck) * g.sz + int64_t(nj) * g.sy + ni;
     const bool emit = own && ck >= k0;
     typename Epi::Pre pre;
@@ -246,9 +252,6 @@ __global__ __launch_bounds__(CX * CY) void hex8_cell_kernel(MechGrid M, const T 
       pre = epi.load(n);
       fix = M.fixed[n];
     }
-    const int m = mid;    // cell layer ck (staged with plane ck + 1)
-    const T hz = m >= 0 ? T(g.dz[ck]) : T(1);
-    __syncthreads();
     T ux[8], uy[8], uz[8];
     T lam = T(0), mu = T(-1);
     if (m >= 0) {
