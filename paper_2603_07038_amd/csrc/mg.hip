@@ -89,33 +89,54 @@ __device__ __forceinline__ void stencil_block(const MgLevel<T> &L, int64_t n, in
   }
 }
 
-// y = A x at node (i,j,k) of a stencil level.
+// y = A x at node (i,j,k) of a stencil level, the 27 offsets in order.  The
+// offsets of one row (ox = -1, 0, 1) are loaded together before they are
+// used: an offset outside the level reads the node's own entries (always
+// finite) with x = 0, so no load waits behind a branch and a row's loads
+// overlap (nine round trips to memory per node instead of 27).  The rows
+// stay a loop: unrolled, all 27 offsets' loads are hoisted together and take
+// 177 registers (2 waves per SIMD).  Adding the masked zeros leaves the
+// sums unchanged.
 template <typename T>
 __device__ __forceinline__ void stencil_apply(const MgLevel<T> &L, int i, int j, int k, int64_t n, const V3<T> &x,
                                               T y[3]) {
   const int64_t N = L.n;
   T y0 = T(0), y1 = T(0), y2 = T(0);
+#pragma unroll 1
+  for (int r = 0; r < 9; ++r) {
+    const int oy = r % 3 - 1, oz = r / 3 - 1;
+    const int jj = j + oy, kk = k + oz;
+    const bool row_ok = jj >= 0 && jj <= L.ny && kk >= 0 && kk <= L.nz;
+    T xv[3][3], R[3][3][3];
+    bool tr[3];
 #pragma unroll
-  for (int o = 0; o < 27; ++o) {
-    int ox, oy, oz;
-    off3(o, ox, oy, oz);
-    const int ii = i + ox, jj = j + oy, kk = k + oz;
-    if (ii < 0 || ii > L.nx || jj < 0 || jj > L.ny || kk < 0 || kk > L.nz) continue;
-    const int64_t m = n + ox + oy * L.sy + oz * L.sz;
-    const T x0 = x.c[0][m], x1 = x.c[1][m], x2 = x.c[2][m];
-    // rows of block q at node p (each three contiguous entries)
-    const int q = o >= 13 ? o - 13 : 13 - o;
-    const int64_t p = o >= 13 ? n : m;
-    const T *R0 = L.A + stencil_idx(q, 0, 0, N, p), *R1 = L.A + stencil_idx(q, 1, 0, N, p),
-            *R2 = L.A + stencil_idx(q, 2, 0, N, p);
-    if (o >= 13) {
-      y0 += R0[0] * x0 + R0[1] * x1 + R0[2] * x2;
-      y1 += R1[0] * x0 + R1[1] * x1 + R1[2] * x2;
-      y2 += R2[0] * x0 + R2[1] * x1 + R2[2] * x2;
-    } else {  // the transpose of the block stored at the lower neighbour
-      y0 += R0[0] * x0 + R1[0] * x1 + R2[0] * x2;
-      y1 += R0[1] * x0 + R1[1] * x1 + R2[1] * x2;
-      y2 += R0[2] * x0 + R1[2] * x1 + R2[2] * x2;
+    for (int c = 0; c < 3; ++c) {
+      const int ox = c - 1, o = r * 3 + c;
+      const int ii = i + ox;
+      const bool ok = row_ok && ii >= 0 && ii <= L.nx;
+      const int64_t m = ok ? n + ox + oy * L.sy + oz * L.sz : n;
+      tr[c] = o < 13;  // stored at the lower neighbour: use its transpose
+      const int q = tr[c] ? 13 - o : o - 13;
+      const int64_t p = tr[c] ? m : n;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) xv[c][d] = x.c[d][m];
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) R[c][rr][cc] = L.A[stencil_idx(q, rr, cc, N, p)];
+      if (!ok) xv[c][0] = xv[c][1] = xv[c][2] = T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T x0 = xv[c][0], x1 = xv[c][1], x2 = xv[c][2];
+      T B[3][3];
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) B[rr][cc] = tr[c] ? R[c][cc][rr] : R[c][rr][cc];
+      y0 += B[0][0] * x0 + B[0][1] * x1 + B[0][2] * x2;
+      y1 += B[1][0] * x0 + B[1][1] * x1 + B[1][2] * x2;
+      y2 += B[2][0] * x0 + B[2][1] * x1 + B[2][2] * x2;
     }
   }
   y[0] = y0; y[1] = y1; y[2] = y2;
@@ -542,22 +563,42 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(MgLevel<T> F, V3<T> r,
   plane_node(C.nx, I, J, K);
   if (I > C.nx || J > C.ny) return;
   const int fi0 = F.ax[0].cpos[I], fj0 = F.ax[1].cpos[J], fk0 = F.ax[2].cpos[K];
+  // the 1D weights of the three fine nodes around the coarse node on each
+  // axis first (0 outside the level), then per fine plane its nine nodes'
+  // loads together, summed in the order fk, fj, fi where a zero weight adds
+  // nothing
+  double wi[3], wj[3], wk[3];
+  int fi[3], fj[3], fk[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    fi[q] = fi0 - 1 + q; fj[q] = fj0 - 1 + q; fk[q] = fk0 - 1 + q;
+    const bool oi = fi[q] >= 0 && fi[q] <= F.nx, oj = fj[q] >= 0 && fj[q] <= F.ny, ok = fk[q] >= 0 && fk[q] <= F.nz;
+    if (!oi) fi[q] = fi0;
+    if (!oj) fj[q] = fj0;
+    if (!ok) fk[q] = fk0;
+    wi[q] = oi ? p1(F.ax[0], fi[q], I) : 0.0;
+    wj[q] = oj ? p1(F.ax[1], fj[q], J) : 0.0;
+    wk[q] = ok ? p1(F.ax[2], fk[q], K) : 0.0;
+  }
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int fk = max(fk0 - 1, 0); fk <= min(fk0 + 1, F.nz); ++fk) {
-    const double wk = p1(F.ax[2], fk, K);
-    if (wk == 0.0) continue;
-    for (int fj = max(fj0 - 1, 0); fj <= min(fj0 + 1, F.ny); ++fj) {
-      const double wj = p1(F.ax[1], fj, J);
-      if (wj == 0.0) continue;
-      for (int fi = max(fi0 - 1, 0); fi <= min(fi0 + 1, F.nx); ++fi) {
-        const double wi = p1(F.ax[0], fi, I);
-        if (wi == 0.0) continue;
-        const double w = wi * wj * wk;
-        const int64_t fn = int64_t(fk) * F.sz + int64_t(fj) * F.sy + fi;
-        a0 += w * double(r.c[0][fn]);
-        a1 += w * double(r.c[1][fn]);
-        a2 += w * double(r.c[2][fn]);
-      }
+#pragma unroll 1
+  for (int qk = 0; qk < 3; ++qk) {
+    if (wk[qk] == 0.0) continue;
+    double rv[9][3];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int64_t fn = int64_t(fk[qk]) * F.sz + int64_t(fj[t / 3]) * F.sy + fi[t % 3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rv[t][c] = double(r.c[c][fn]);
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const double wjj = wj[t / 3], wii = wi[t % 3];
+      if (wjj == 0.0 || wii == 0.0) continue;
+      const double w = wii * wjj * wk[qk];
+      a0 += w * rv[t][0];
+      a1 += w * rv[t][1];
+      a2 += w * rv[t][2];
     }
   }
   const int64_t cn = int64_t(K) * C.sz + int64_t(J) * C.sy + I;
@@ -582,16 +623,26 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(MgLevel<T> F, V3<T> x, 
   const double wx[2] = {F.ax[0].w[i], 1.0 - F.ax[0].w[i]};
   const double wy[2] = {F.ax[1].w[j], 1.0 - F.ax[1].w[j]};
   const double wz[2] = {F.ax[2].w[k], 1.0 - F.ax[2].w[k]};
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  // the eight corners' loads first (a corner of weight 0 may lie past the
+  // last coarse node: it reads the first corner instead), then the sums in
+  // corner order, where a zero weight adds nothing
+  double w[8], xv[8][3];
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
     const int tx = t & 1, ty = (t >> 1) & 1, tz = t >> 2;
-    const double w = wx[tx] * wy[ty] * wz[tz];
-    if (w == 0.0) continue;
-    const int64_t cn = int64_t(lz + tz) * C.sz + int64_t(ly + ty) * C.sy + (lx + tx);
-    a0 += w * double(xc.c[0][cn]);
-    a1 += w * double(xc.c[1][cn]);
-    a2 += w * double(xc.c[2][cn]);
+    w[t] = wx[tx] * wy[ty] * wz[tz];
+    const int64_t cn = w[t] != 0.0 ? int64_t(lz + tz) * C.sz + int64_t(ly + ty) * C.sy + (lx + tx)
+                                   : int64_t(lz) * C.sz + int64_t(ly) * C.sy + lx;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xv[t][c] = double(xc.c[c][cn]);
+  }
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    if (w[t] == 0.0) continue;
+    a0 += w[t] * xv[t][0];
+    a1 += w[t] * xv[t][1];
+    a2 += w[t] * xv[t][2];
   }
   const uint8_t dd = F.dead[n];
   if (!(dd & 1)) x.c[0][n] += T(a0);
@@ -627,8 +678,18 @@ __global__ __launch_bounds__(256) void mg_dense_kernel(const T *Ainv, const int3
   const int lane = threadIdx.x % kDenseRows, part = threadIdx.x / kDenseRows;
   const int r = blockIdx.x * kDenseRows + lane;
   double acc = 0.0;
-  if (r < nl)
-    for (int j = part; j < nl; j += kDenseParts) acc += double(Ainv[int64_t(j) * nl + r]) * bs[j];
+  if (r < nl) {
+    // eight loads in flight, summed in the same order
+    int j = part;
+    for (; j + 7 * kDenseParts < nl; j += 8 * kDenseParts) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = double(Ainv[int64_t(j + u * kDenseParts) * nl + r]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += a[u] * bs[j + u * kDenseParts];
+    }
+    for (; j < nl; j += kDenseParts) acc += double(Ainv[int64_t(j) * nl + r]) * bs[j];
+  }
   red[part][lane] = acc;
   __syncthreads();
   if (part == 0 && r < nl) {
