@@ -747,6 +747,27 @@ struct EpiSmooth0 {
   }
 };
 
+// The last post-smoothing step of a V-cycle that CG applies to its residual
+// b = r: also the dot product r . z of the result z = x_out (per-block sums
+// into the partials), so no separate pass reads r and z again.
+template <typename T>
+struct EpiSmooth0Dot : EpiSmooth0<T> {
+  __device__ void operator()(int64_t n, const T y[3], const T xc[3], const typename EpiSmooth0<T>::Pre &q,
+                             double *red) const {
+    const T r[3] = {q.b[0] - y[0], q.b[1] - y[1], q.b[2] - y[2]};
+    T z[3];
+    dinv_apply<T>(q.D, r, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T dn = this->c2 * z[c] + this->c1 * q.d[c];
+      this->L.d.c[c][n] = dn;
+      const T xo = xc[c] + dn;
+      this->xout.c[c][n] = xo;
+      red[0] += double(q.b[c]) * double(xo);
+    }
+  }
+};
+
 template <typename T>
 struct EpiResid0 {
   V3<T> b, r;
@@ -922,9 +943,11 @@ inline int64_t lblocks(const MgLevel<T> &L) {
 
 template <typename T>
 hipError_t smooth(const MgDev<T> &G, int l, V3<T> b, V3<T> xin, V3<T> xout, int step, int first,
-                  const DevScalars *sc, hipStream_t s) {
+                  const DevScalars *sc, hipStream_t s, double *dot_partials = nullptr) {
   const MgLevel<T> &L = G.L[l];
   const T c1 = T(L.c1[step]), c2 = T(L.c2[step]);
+  if (l == 0 && !first && dot_partials)
+    return launch_hex8<T, 1>(G.M, xin.c, EpiSmooth0Dot<T>{{L, b, xout, c1, c2}}, dot_partials, sc, s);
   if (l == 0 && !first)
     return launch_hex8<T, 0>(G.M, xin.c, EpiSmooth0<T>{L, b, xout, c1, c2}, nullptr, sc, s);
   hipLaunchKernelGGL((mg_smooth_kernel<T>), lgrid(L), dim3(BX, BY), 0, s, L, b, xin, xout, c1, c2, first, sc);
@@ -935,7 +958,7 @@ hipError_t smooth(const MgDev<T> &G, int l, V3<T> b, V3<T> xin, V3<T> xout, int 
 // level 0 inside the CG kernel that forms r (first_done).
 template <typename T>
 hipError_t vcycle_level(const MgDev<T> &G, int l, V3<T> b, const DevScalars *sc, V3<T> *out, hipStream_t s,
-                        bool first_done) {
+                        bool first_done, double *dot_partials = nullptr) {
   const MgLevel<T> &L = G.L[l];
   hipError_t e;
   if (l == G.nlev - 1) {
@@ -966,7 +989,9 @@ hipError_t vcycle_level(const MgDev<T> &G, int l, V3<T> b, const DevScalars *sc,
   if ((e = vcycle_level(G, l + 1, C.b, sc, &xcoarse, s, fuse != 0)) != hipSuccess) return e;
   hipLaunchKernelGGL((mg_prolong_kernel<T>), lgrid(L), dim3(BX, BY), 0, s, L, xc, C, xcoarse, sc);
   for (int k = 0; k < L.deg; ++k) {
-    if ((e = smooth(G, l, b, xc, xo, k, 0, sc, s)) != hipSuccess) return e;
+    // with dot_partials (level 0 of a CG step): the last step also forms b . out
+    double *dp = (l == 0 && k + 1 == L.deg) ? dot_partials : nullptr;
+    if ((e = smooth(G, l, b, xc, xo, k, 0, sc, s, dp)) != hipSuccess) return e;
     std::swap(xc, xo);
   }
   *out = xc;
@@ -1044,10 +1069,12 @@ hipError_t launch_cgmg_setup(const MgDev<T> &G, const CgVecs<T> &v, const T *rhs
   // the rest of the setup runs only after a restart that left work to do
   const DevScalars *g2 = gate ? (const DevScalars *)gate : (const DevScalars *)sc;
   V3<T> r{{v.r[0], v.r[1], v.r[2]}}, z;
-  hipError_t e = vcycle_level(G, 0, r, g2, &z, s, fuse != 0);
+  // with more than one level the V-cycle's last level-0 step forms r . z
+  hipError_t e = vcycle_level(G, 0, r, g2, &z, s, fuse != 0, fuse ? partials : nullptr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((cgmg_dot_kernel<T>), lgrid(L0), dim3(BX, BY), 0, s, G.M, v, z, g2, partials);
-  hipLaunchKernelGGL(cgmg_rz_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc, 1, g2);
+  if (!fuse) hipLaunchKernelGGL((cgmg_dot_kernel<T>), lgrid(L0), dim3(BX, BY), 0, s, G.M, v, z, g2, partials);
+  hipLaunchKernelGGL(cgmg_rz_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
+                     fuse ? cell_blocks(G.M.g, cell_kchunk(G.M.g)) : nb, sc, 1, g2);
   hipLaunchKernelGGL((cgmg_p_kernel<T>), dim3(flat_blocks(L0.n)), dim3(256), 0, s, v, z, L0.n,
                      (const DevScalars *)sc, 1, g2);
   return hipGetLastError();
@@ -1066,11 +1093,13 @@ hipError_t launch_cgmg_iteration(const MgDev<T> &G, const CgVecs<T> &v, double *
                      (const DevScalars *)sc, partials);
   hipLaunchKernelGGL(cgmg_rr_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, int64_t(fb), sc);
   V3<T> r{{v.r[0], v.r[1], v.r[2]}}, z;
-  if ((e = vcycle_level(G, 0, r, sc, &z, s, fuse != 0)) != hipSuccess) return e;
-  hipLaunchKernelGGL((cgmg_dot_kernel<T>), lgrid(L0), dim3(BX, BY), 0, s, G.M, v, z, (const DevScalars *)sc,
-                     partials);
-  hipLaunchKernelGGL(cgmg_rz_finalize, dim3(1), dim3(256), 0, s, (const double *)partials, nb, sc, 0,
-                     (const DevScalars *)nullptr);
+  // with more than one level the V-cycle's last level-0 step forms r . z
+  if ((e = vcycle_level(G, 0, r, sc, &z, s, fuse != 0, fuse ? partials : nullptr)) != hipSuccess) return e;
+  if (!fuse)
+    hipLaunchKernelGGL((cgmg_dot_kernel<T>), lgrid(L0), dim3(BX, BY), 0, s, G.M, v, z, (const DevScalars *)sc,
+                       partials);
+  hipLaunchKernelGGL(cgmg_rz_finalize, dim3(1), dim3(256), 0, s, (const double *)partials,
+                     fuse ? cell_blocks(G.M.g, cell_kchunk(G.M.g)) : nb, sc, 0, (const DevScalars *)nullptr);
   hipLaunchKernelGGL((cgmg_p_kernel<T>), dim3(fb), dim3(256), 0, s, v, z, L0.n, (const DevScalars *)sc, 0,
                      (const DevScalars *)nullptr);
   return hipGetLastError();
