@@ -292,7 +292,14 @@ void etm_plan_destroy(etm_plan *plan);
  * single launch that walks a (variant, tile) work list, each thermal block a
  * single launch; chunks of steps are captured once in a HIP graph and
  * replayed.  A variant's results are bitwise those of its solo run.
- * tune_json may name per-shape tile choices ("{}" or NULL: defaults). */
+ * tune_json (NULL or "{}": defaults) is the autotuner's table of tile shapes
+ * per size class, the class being floor(log2(cells)) of a variant:
+ *   {"kchunk": {"<class>": planes, ...}, "layout": {"<class>": 1 | 2, ...}}
+ * kchunk (1..128) is the z-chunk of the march tiles; layout (mixed precision
+ * only) makes the waves take runs of 62 nodes over the plane numbered x
+ * fastest (1) or 62-node segments of rows, 4 rows per block (2).  Entries out
+ * of range and malformed text are ignored; no choice changes results.  The
+ * string is read at creation and not kept. */
 etm_status etm_batch_create(int32_t max_slots, const char *tune_json, etm_batch **out);
 etm_status etm_batch_attach(etm_batch *batch, etm_plan *plan, int32_t *slot);
 etm_status etm_batch_detach(etm_batch *batch, int32_t slot);
