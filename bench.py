@@ -593,6 +593,19 @@ def cpu_legs(prob3, dt3):
     el2 = time.perf_counter() - t
     out["slice256x256x64_coupled"] = {"mcell_steps_per_s": round(p2.n_cells * 15 / el2 / 1e6, 3),
                                       "sample": "EM steps 2-16 with the thermal step at step 16", "s": round(el2, 2)}
+    # the slice's mechanics: one application of K (a Jacobi-PCG iteration's
+    # dominant work) with element matrices formed on the fly; the oracle's
+    # solver would first cache them (576 doubles per cell, 19 GB here)
+    mask2 = o2.mech_mask()
+    q2 = np.zeros(tuple(o2.node_shape) + (3,))
+    q2[..., 2] = 1e-9
+    t = time.perf_counter()
+    o2.mech_apply(mask2, q2)
+    el_k = time.perf_counter() - t
+    dofs2 = 3 * int(np.prod(o2.node_shape))
+    out["slice256x256x64_cg"] = {"dof_iter_per_s": round(dofs2 / el_k, 1), "apply_s": round(el_k, 2),
+                                 "sample": "one K application (HEX8 elements formed per cell), the cost of a "
+                                           "Jacobi-PCG iteration without the element cache"}
     del o2
     # the 32x32x16 trace case in full: 2000 steps at R = 200, one solve
     p1 = W.config1()
