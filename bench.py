@@ -48,8 +48,10 @@ Further legs (on by default; --legs selects):
              at 2, 5, 10 and 20 req/s);
   cpu        the FP64 oracle on the host cores: a bounded window of the
              package (one EM step, Joule and a thermal step), a sample of the
-             slice with its thermal step, the full 32x32x16 trace case, and
-             the oracle's CG DOF-iterations/s on the 32x32x16 case.
+             slice with its thermal step, the full 32x32x16 trace case, the
+             oracle's CG DOF-iterations/s on the 32x32x16 case, and one
+             application of the slice's stiffness (its Jacobi-PCG rate without
+             the element cache).
 
     python bench.py [--steps K] [--warmup W] [--legs headline,slice,...] [--no-cpu]
 """
