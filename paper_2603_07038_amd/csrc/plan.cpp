@@ -332,13 +332,25 @@ etm_status derive(etm_plan *p, const etm_source *src) {
     uint8_t mbits[256] = {};
     for (int m = 0; m < p->n_mat; ++m)
       if (p->mats[m].sigma0 != 0.0) mbits[m] = uint8_t(kFlagSigma | (p->mats[m].tcr != 0.0 ? kFlagTcr : 0));
+    // per cell row: the bits of each node of the row's line (a node takes
+    // the cells on both sides), then or-ed into the four node lines that
+    // bound the row
+    std::vector<uint8_t> nb(size_t(nx) + 1);
     for (int k = 0; k < nz; ++k)
       for (int j = 0; j < ny; ++j) {
         const uint8_t *row = &p->mat_nat[(size_t(k) * ny + j) * nx];
+        uint8_t any = 0, prev = 0;
         for (int i = 0; i < nx; ++i) {
           const uint8_t b = mbits[row[i]];
-          if (!b) continue;
-          for (int c = 0; c < 8; ++c) p->flags[p->nidx(i + (c & 1), j + ((c >> 1) & 1), k + (c >> 2))] |= b;
+          nb[i] = uint8_t(prev | b);
+          prev = b;
+          any |= b;
+        }
+        nb[nx] = prev;
+        if (!any) continue;
+        for (int c = 0; c < 4; ++c) {
+          uint8_t *line = &p->flags[p->nidx(0, j + (c & 1), k + (c >> 1))];
+          for (int i = 0; i <= nx; ++i) line[i] |= nb[i];
         }
       }
   }
