@@ -81,6 +81,21 @@ def time_class(c: int, steps: int, precision: int):
     return res, copies, p.n_cells
 
 
+TIE = 0.02  # candidates within 2 % of the fastest count as tied
+
+
+def pick(res):
+    """The (layout, chunk) to use: among the candidates within TIE of the
+    fastest, the longest chunk (fewest work items and least halo traffic: a
+    chunk stages one plane beyond its own), runs before row segments.  The
+    classes are timed in batches of one size; in a batch of mixed sizes, as
+    the server runs, the shorter of two tied chunks measured up to 8 % slower
+    per design."""
+    best = min(res.values())
+    tied = [key for key, v in res.items() if v <= (1.0 + TIE) * best]
+    return max(tied, key=lambda key: (key[1], key[0] == 1))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_TABLE)
@@ -94,7 +109,7 @@ def main(argv=None):
     table = {"kchunk": {}, "layout": {}, "timings_us": {}, "precision": a.precision, "candidates": list(CANDIDATES)}
     for c in range(lo, hi + 1):
         res, copies, cells = time_class(c, a.steps, prec)
-        lay, kc = min(res, key=res.get)
+        lay, kc = pick(res)
         table["kchunk"][str(c)] = kc
         if lay:
             table["layout"][str(c)] = lay
