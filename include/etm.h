@@ -294,10 +294,12 @@ void etm_plan_destroy(etm_plan *plan);
  * replayed.  A variant's results are bitwise those of its solo run.
  * tune_json (NULL or "{}": defaults) is the autotuner's table of tile shapes
  * per size class, the class being floor(log2(cells)) of a variant:
- *   {"kchunk": {"<class>": planes, ...}, "layout": {"<class>": 1 | 2, ...}}
- * kchunk (1..128) is the z-chunk of the march tiles; layout (mixed precision
- * only) makes the waves take runs of 62 nodes over the plane numbered x
- * fastest (1) or 62-node segments of rows, 4 rows per block (2).  Entries out
+ *   {"kchunk": {"<class>": planes, ...}, "layout": {"<class>": 1 | 2, ...},
+ *    "kchunk_fp64": {"<class>": planes, ...}}
+ * kchunk (1..128) is the z-chunk of the mixed-precision march tiles and
+ * kchunk_fp64 that of the FP64 tiles; layout (mixed precision only) makes
+ * the waves take runs of 62 nodes over the plane numbered x fastest (1) or
+ * 62-node segments of rows, 4 rows per block (2).  Entries out
  * of range and malformed text are ignored; no choice changes results.  The
  * string is read at creation and not kept. */
 etm_status etm_batch_create(int32_t max_slots, const char *tune_json, etm_batch **out);

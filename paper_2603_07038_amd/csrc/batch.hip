@@ -15,7 +15,8 @@
 // The tile shape per variant -- its z-chunk length and, in mixed precision,
 // its work layout (runs over the x-fastest plane or row segments) -- comes
 // from a tuning table keyed by the variant's size class
-// ("{\"kchunk\": {\"<log2 cells>\": k, ...}, \"layout\": {\"<log2 cells>\": 1 or 2}}"),
+// ("{\"kchunk\": {\"<log2 cells>\": k, ...}, \"layout\": {\"<log2 cells>\": 1 or 2},
+// \"kchunk_fp64\": {...}}"; "kchunk" serves mixed precision),
 // written by the package's autotuner; without an entry the automatic choice
 // is used.
 //
@@ -46,7 +47,8 @@ constexpr int kStageRing = 8;
 struct etm_batch {
   int32_t max_slots = 0;
   std::vector<etm_plan *> slots;
-  std::map<int, int> kchunk_by_class;
+  std::map<int, int> kchunk_by_class;       // mixed precision
+  std::map<int, int> kchunk_fp64_by_class;  // FP64
   std::map<int, int> layout_by_class;
   // device
   BatchVar *d_vars = nullptr;
@@ -121,8 +123,9 @@ void order_variants(etm_batch *b) {
     etm_plan *p = b->slots[slot];
     auto lt = b->layout_by_class.find(size_class(p));
     p->layout = lt != b->layout_by_class.end() ? lt->second : kLayoutAuto;
-    auto it = b->kchunk_by_class.find(size_class(p));
-    p->kchunk = it != b->kchunk_by_class.end() ? it->second : em_kchunk(p->dev_grid(), b->precision);
+    const std::map<int, int> &km = b->precision == ETM_PREC_FP64 ? b->kchunk_fp64_by_class : b->kchunk_by_class;
+    auto it = km.find(size_class(p));
+    p->kchunk = it != km.end() ? it->second : em_kchunk(p->dev_grid(), b->precision);
   }
 }
 
@@ -378,6 +381,7 @@ etm_status etm_batch_create(int32_t max_slots, const char *tune_json, etm_batch 
   b->own.assign(max_slots, nullptr);
   b->old_cur.assign(max_slots, 0);
   parse_tune(tune_json, "\"kchunk\"", 1, 128, b->kchunk_by_class);
+  parse_tune(tune_json, "\"kchunk_fp64\"", 1, 128, b->kchunk_fp64_by_class);
   parse_tune(tune_json, "\"layout\"", kLayoutRuns, kLayoutRows, b->layout_by_class);
   hipError_t e = hipGetDevice(&b->device);
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_vars, sizeof(BatchVar) * max_slots);

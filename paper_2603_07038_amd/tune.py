@@ -13,10 +13,11 @@ segments share the rows j - 1, j + 1 of their neighbours in L2.  For each
 size class (floor of log2 of the cell count, the key the batch uses) a
 package variant of that size is replicated until the batch holds at least
 16 M cells, and every candidate (layout, chunk) is timed over graph-replayed
-EM steps.  The fastest per class is written as
+EM steps.  The choice per class (see ``pick``) is written as
 ``{"kchunk": {"<class>": k, ...}, "layout": {"<class>": 1 or 2, ...},
-"timings_us": {...}}``, the table ``Batch`` reads (``tune_gfx950.json`` next
-to this file by default).  Every layout and chunk gives bitwise the same
+"kchunk_fp64": {...}, "timings_us": {...}, "timings_fp64_us": {...}}`` (a
+run updates its own precision's maps), the table ``Batch`` reads
+(``tune_gfx950.json`` next to this file by default).  Every layout and chunk gives bitwise the same
 results, so the table changes speed only.
 """
 from __future__ import annotations
@@ -106,17 +107,29 @@ def main(argv=None):
     from . import ETM_PREC_FP64, ETM_PREC_MIXED
     prec = ETM_PREC_MIXED if a.precision == "mixed" else ETM_PREC_FP64
     lo, hi = (int(x) for x in a.classes.split("-"))
-    table = {"kchunk": {}, "layout": {}, "timings_us": {}, "precision": a.precision, "candidates": list(CANDIDATES)}
+    # one table for both precisions: this run replaces its own precision's maps
+    table = {}
+    if os.path.exists(a.out):
+        with open(a.out) as f:
+            table = json.load(f)
+    sfx = "" if a.precision == "mixed" else "_fp64"
+    kmap, lmap, tmap = {}, {}, {}
     for c in range(lo, hi + 1):
         res, copies, cells = time_class(c, a.steps, prec)
         lay, kc = pick(res)
-        table["kchunk"][str(c)] = kc
+        kmap[str(c)] = kc
         if lay:
-            table["layout"][str(c)] = lay
-        table["timings_us"][str(c)] = {f"{'runs' if l == 1 else 'rows' if l == 2 else 'tile'}/{k}": round(v, 2)
-                                      for (l, k), v in res.items()}
+            lmap[str(c)] = lay
+        tmap[str(c)] = {f"{'runs' if l == 1 else 'rows' if l == 2 else 'tile'}/{k}": round(v, 2)
+                        for (l, k), v in res.items()}
         print(json.dumps({"class": c, "cells": cells, "copies": copies, "best": [lay, kc],
-                          "us_per_step": table["timings_us"][str(c)]}), flush=True)
+                          "us_per_step": tmap[str(c)]}), flush=True)
+    table["kchunk" + sfx] = kmap
+    if a.precision == "mixed":
+        table["layout"] = lmap
+    table["timings" + sfx + "_us"] = tmap
+    table["candidates"] = list(CANDIDATES)
+    table.pop("precision", None)
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1)
     print("wrote", a.out)

@@ -154,6 +154,7 @@ int main() {
       "{\"kchunk\": {\"5\": 999, \"6\": -1, \"x\": \"y\"}}", "\"kchunk\":}", "{\"kchunk\": {\"1\": 4}, \"kchunk\": 3}",
       "{\"kchunk\": {\"17\": 8}, \"layout\": {\"17\": 2, \"18\": 1, \"19\": 7}}", "{\"layout\": {\"",
       "{\"layout\"", "{\"layout\": {\"3\": }",
+      "{\"kchunk\": {\"17\": 6}, \"kchunk_fp64\": {\"17\": 24, \"20\": 2, \"21\": 0}}", "{\"kchunk_fp64\": {",
   };
   for (const char *t : tunes) {
     etm_batch *b = reinterpret_cast<etm_batch *>(0x1);
