@@ -299,9 +299,10 @@ void etm_plan_destroy(etm_plan *plan);
  * kchunk (1..128) is the z-chunk of the mixed-precision march tiles and
  * kchunk_fp64 that of the FP64 tiles; layout (mixed precision only) makes
  * the waves take runs of 62 nodes over the plane numbered x fastest (1) or
- * 62-node segments of rows, 4 rows per block (2).  Entries out
- * of range and malformed text are ignored; no choice changes results.  The
- * string is read at creation and not kept. */
+ * 62-node segments of rows, 4 rows per block (2).  A class without an entry
+ * takes the chunk the library picks from the variant's tile count.  Entries
+ * out of range and malformed text are ignored; no choice changes results.
+ * The string is read at creation and not kept. */
 etm_status etm_batch_create(int32_t max_slots, const char *tune_json, etm_batch **out);
 etm_status etm_batch_attach(etm_batch *batch, etm_plan *plan, int32_t *slot);
 etm_status etm_batch_detach(etm_batch *batch, int32_t slot);

@@ -223,4 +223,6 @@ def summarize(results: List[Result], wall: float) -> dict:
             "failed": sum(r.status == "error" for r in results),
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "mean_s": float(lat.mean()), "designs_per_hour": len(ok) / wall * 3600.0 if wall > 0 else None,
-            "cell_steps": int(sum(r.cells * r.em_steps for r in ok)), "wall_s": wall}
+            "cell_steps": int(sum(r.cells * r.em_steps for r in ok)), "wall_s": wall,
+            "cg_iters_mean": float(np.mean([r.cg_iters for r in ok])) if ok else None,
+            "cg_iters_max": int(max(r.cg_iters for r in ok)) if ok else None}

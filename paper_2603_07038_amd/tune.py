@@ -15,10 +15,18 @@ package variant of that size is replicated until the batch holds at least
 16 M cells, and every candidate (layout, chunk) is timed over graph-replayed
 EM steps.  The choice per class (see ``pick``) is written as
 ``{"kchunk": {"<class>": k, ...}, "layout": {"<class>": 1 or 2, ...},
-"kchunk_fp64": {...}, "timings_us": {...}, "timings_fp64_us": {...}}`` (a
-run updates its own precision's maps), the table ``Batch`` reads
-(``tune_gfx950.json`` next to this file by default).  Every layout and chunk gives bitwise the same
+"timings_us": {...}, "timings_fp64_us": {...}}`` (a run updates its own
+precision's entries), the table ``Batch`` reads (``tune_gfx950.json`` next to
+this file by default).  Every layout and chunk gives bitwise the same
 results, so the table changes speed only.
+
+An FP64 run records its timings but writes its picks (``"kchunk_fp64"``)
+only with ``--fp64-map``: on gfx950 the FP64 chunks are within 1 % of each
+other up to 0.75 M cells and 2 planes win above, yet served in batches of
+mixed sizes the picks (24 and 2 planes), uniform 2-plane chunks and the
+mixed-precision table all gave fewer designs per hour than the batch's own
+rule for chunks without an entry (9.5 k, 9.9 k and 10.4 k against 11.2 k at
+saturation).
 """
 from __future__ import annotations
 
@@ -103,6 +111,7 @@ def main(argv=None):
     ap.add_argument("--classes", default="15-24")
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--fp64-map", action="store_true", help="write the FP64 picks, not only their timings")
     a = ap.parse_args(argv)
     from . import ETM_PREC_FP64, ETM_PREC_MIXED
     prec = ETM_PREC_MIXED if a.precision == "mixed" else ETM_PREC_FP64
@@ -124,9 +133,11 @@ def main(argv=None):
                         for (l, k), v in res.items()}
         print(json.dumps({"class": c, "cells": cells, "copies": copies, "best": [lay, kc],
                           "us_per_step": tmap[str(c)]}), flush=True)
-    table["kchunk" + sfx] = kmap
     if a.precision == "mixed":
+        table["kchunk"] = kmap
         table["layout"] = lmap
+    elif a.fp64_map:
+        table["kchunk_fp64"] = kmap
     table["timings" + sfx + "_us"] = tmap
     table["candidates"] = list(CANDIDATES)
     table.pop("precision", None)
