@@ -656,20 +656,37 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
   const bool fx = inb && j < ny;                   // x-normal (i, j, k), k < nz
   const bool fxm = inb && jm_ok;                   // x-normal (i, j - 1, k), k < nz
 
-  // (the coefficients and K are read whatever the node's flags: gating these
-  // loads on the flags measured slower here, unlike in the FP64 tile)
-  auto load_node = [&](int kk, YeeNode &c) {
+  // A node with no conducting cell around it has 2a = 0 on its own edges,
+  // on the y-edge of its j - 1 neighbour and (through the previous lane and
+  // plane) on the other incident edges, and K = 0: a wave none of whose
+  // nodes has a conducting cell skips those loads.  The test is wave-wide
+  // (a scalar branch) and reads flags loaded one plane ahead, so no load
+  // waits behind it; gating the loads lane by lane measured slower.
+  auto load_flags = [&](int kk) -> uint8_t { return g.flags[uint32_t(min(kk, nz)) * sz + rj] & (7 | kFlagSigma); };
+  auto load_node = [&](int kk, uint8_t flk, YeeNode &c) {
     const uint32_t n = uint32_t(kk) * sz + rj;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       c.er[d] = cf[d * cs + n];
-      c.a2[d] = cf[(3 + d) * cs + n];
-      c.K[d] = Kp ? Kp[d * cs + n] : 0.0f;
       c.lo[d] = elo[d * cs + n];
     }
+    c.fl = flk;
     c.a2xm = 0.0f;  // from the previous lane
-    c.a2ym = cf[4 * cs + uint32_t(kk) * sz + rm];
-    c.fl = g.flags[n] & (7 | kFlagSigma);
+    if (__any(flk & kFlagSigma)) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        c.a2[d] = cf[(3 + d) * cs + n];
+        c.K[d] = Kp ? Kp[d * cs + n] : 0.0f;
+      }
+      c.a2ym = cf[4 * cs + uint32_t(kk) * sz + rm];
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        c.a2[d] = 0.0f;
+        c.K[d] = 0.0f;
+      }
+      c.a2ym = 0.0f;
+    }
   };
   struct Hold {
     float x, y, z, xm, zm;  // old faces at (i, j, k) and at (i, j - 1, k)
@@ -689,7 +706,8 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
   float p0x = ld(p.e, k0, rp, jp_ok), p0z = ld(p.e + 2 * cs, k0, rp, jp_ok);
   float p1x = ld(p.e, k0 + 1, rp, jp_ok), p1z = ld(p.e + 2 * cs, k0 + 1, rp, jp_ok);
   YeeNode nd;
-  load_node(k0, nd);
+  load_node(k0, load_flags(k0), nd);
+  uint8_t fl_next = load_flags(k0 + 1);  // flags of the plane after nd's
   Hold ho;
   load_hold(k0, ho);
   float ezm = 0.0f, hy_km = 0.0f, hx_km = 0.0f, a2zm = 0.0f;
@@ -799,7 +817,10 @@ __device__ __forceinline__ void em_march_row_yee(const EmLaunch &L, const EmPtrs
     hy_km = hy_c;
     hx_km = hx_c;
     a2zm = nd.a2[2];
-    if (k + 1 < k1) load_node(k + 1, nd);
+    if (k + 1 < k1) {
+      load_node(k + 1, fl_next, nd);
+      fl_next = load_flags(k + 2);
+    }
     c0 = c1; c1 = c2;
     m0 = m1; m1 = m2;
     p0x = p1x; p0z = p1z; p1x = p2x; p1z = p2z;
