@@ -23,10 +23,9 @@ results, so the table changes speed only.
 An FP64 run records its timings but writes its picks (``"kchunk_fp64"``)
 only with ``--fp64-map``: on gfx950 the FP64 chunks are within 1 % of each
 other up to 0.75 M cells and 2 planes win above, yet served in batches of
-mixed sizes the picks (24 and 2 planes), uniform 2-plane chunks and the
-mixed-precision table all gave fewer designs per hour than the batch's own
-rule for chunks without an entry (9.5 k, 9.9 k and 10.4 k against 11.2 k at
-saturation).
+mixed sizes the picks (24 and 2 planes) gave fewer designs per hour than the
+batch's own rule for chunks without an entry (10.8 k against 12.7 k at
+saturation; uniform 2-plane chunks and the mixed-precision table also lost).
 """
 from __future__ import annotations
 
