@@ -19,9 +19,9 @@ import numpy as np
 
 # ---------------------------------------------------------------------------
 # Material table.  Columns follow the order below; ``void`` = 1 marks a cell
-# that carries no stiffness (air).  Values marked "proposed" in the design doc are
-# not in the paper; Cu/Si/solder E and CTE follow the paper's materials list
-# (Sec. III-A), and the package-slice values follow the workload recipes.
+# that carries no stiffness (air).  Cu/Si/solder E and CTE follow the paper's
+# materials list (Sec. III-A); the dielectric, thermal and polymer values,
+# which the paper does not list, are typical figures for these materials.
 # ---------------------------------------------------------------------------
 PROP_COLUMNS = ("eps_r", "sigma0", "tcr", "k", "rho_cp", "E", "nu", "cte", "void")
 N_PROP = len(PROP_COLUMNS)
