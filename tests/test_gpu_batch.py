@@ -31,11 +31,13 @@ def _size_class(p):
     return int(np.floor(np.log2(p.n_cells)))
 
 
-@pytest.mark.parametrize("prec,layout", [(etm.ETM_PREC_FP64, None), (etm.ETM_PREC_MIXED, None),
-                                         (etm.ETM_PREC_MIXED, 1), (etm.ETM_PREC_MIXED, 2)])
+@pytest.mark.parametrize("prec,layout", [(etm.ETM_PREC_FP64, None), (etm.ETM_PREC_FP64, 0),
+                                         (etm.ETM_PREC_MIXED, None), (etm.ETM_PREC_MIXED, 1),
+                                         (etm.ETM_PREC_MIXED, 2)])
 def test_batch_matches_solo_bitwise(prec, layout):
     """layout None: the default tuning table; 1 / 2: every variant forced to
-    runs over the x-fastest plane / row segments (with odd z-chunks)."""
+    runs over the x-fastest plane / row segments (with odd z-chunks); 0 (FP64):
+    odd z-chunks from the FP64 chunk map."""
     probs = _variants(5)
     print(f"[batch] prec={prec} layout={layout} variants={[p.name for p in probs]}", flush=True)
     dts = [etm.cfl_dt(p) for p in probs]
@@ -46,12 +48,14 @@ def test_batch_matches_solo_bitwise(prec, layout):
         pl.advance(23)
         pl.advance(37)
         solo.append(_state(pl))
+    classes = sorted({_size_class(p) for p in probs})
+    odd = {str(c): [3, 5, 2][c % 3] for c in classes}
     if layout is None:
         b = etm.Batch(8)
+    elif layout == 0:
+        b = etm.Batch(8, json.dumps({"kchunk_fp64": odd}))
     else:
-        classes = sorted({_size_class(p) for p in probs})
-        b = etm.Batch(8, json.dumps({"kchunk": {str(c): [3, 5, 2][c % 3] for c in classes},
-                                     "layout": {str(c): layout for c in classes}}))
+        b = etm.Batch(8, json.dumps({"kchunk": odd, "layout": {str(c): layout for c in classes}}))
     plans = []
     for p, dt, J in zip(probs, dts, Js):
         pl = etm.Plan(p, J, dt=dt, precision=prec, n_steps=60, history=False)
