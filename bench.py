@@ -556,14 +556,21 @@ def serve_leg(n_requests, rates, precisions=("mixed", "fp64")):
         res["rates"][str(rate)] = one
     for name in precisions:
         pts = [(float(r), v[name]) for r, v in res["rates"].items() if name in v]
-        pts.sort()
-        if len(pts) < 2:   # a knee needs a sweep
-            continue
-        p99_0 = pts[0][1]["p99_s"]
-        ok = [r for r, v in pts if v["p99_s"] <= 2.0 * p99_0 and (v["sustained_frac"] or 0.0) >= 0.9]
-        res[f"knee_{name}_req_per_s"] = max(ok) if ok else None
+        if len(pts) >= 2:   # a knee needs a sweep
+            res[f"knee_{name}_req_per_s"] = serving_knee(pts)
     res["knee_rule"] = "highest rate with p99 <= 2x the p99 at the lowest rate and >= 90% of the offered rate answered"
     return res
+
+
+def serving_knee(pts):
+    """The knee of a serving sweep: ``pts`` is a list of (offered rate,
+    summary with "p99_s" and "sustained_frac"); returns the highest rate whose
+    p99 latency is at most twice the p99 at the lowest rate while at least
+    90 % of the offered rate is answered, or None."""
+    pts = sorted(pts, key=lambda x: x[0])
+    p99_0 = pts[0][1]["p99_s"]
+    ok = [r for r, v in pts if v["p99_s"] <= 2.0 * p99_0 and (v["sustained_frac"] or 0.0) >= 0.9]
+    return max(ok) if ok else None
 
 
 # ---- the FP64 oracle on the host cores -------------------------------------------
